@@ -1,0 +1,134 @@
+"""Seeded initial fields for the two hot-path workloads and for unit tests.
+
+Workloads (cell units, periodic unit square split into ``n`` cells per side):
+
+* transport workload: eight Gaussian bumps plus one square step, the
+  scalar initial field of the first-order upwind finite-volume run;
+* lattice-Boltzmann workload: a double shear layer with a small sinusoidal
+  transverse perturbation, given as macroscopic density and velocity (the
+  populations are built from them by each side's own equilibrium code).
+
+Every function draws its random numbers from ``numpy.random.default_rng(seed)``
+in the order its docstring states, so the recipe is reproducible from the text.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def fv_gaussians_and_step(n: int = 256, seed: int = 0, n_bumps: int = 8,
+                          sigma_range=(5.0, 20.0), amp_range=(0.5, 1.0),
+                          step_side: int = 64) -> np.ndarray:
+    """Scalar field ``[n, n]`` (float64): Gaussian bumps plus a unit square step.
+
+    Draw order: centres ``(n_bumps, 2)`` uniform in ``[0, n)`` (x then y),
+    widths ``sigma`` uniform in ``sigma_range`` cells, amplitudes uniform in
+    ``amp_range``, then the step's lower-left corner as two integers in
+    ``[0, n)``.  Bump ``k`` is ``A_k exp(-r^2 / (2 sigma_k^2))`` with ``r`` the
+    periodic minimum-image distance between the cell index and the centre.  The
+    step adds 1 on a ``step_side`` x ``step_side`` block that wraps around.
+    The background is 0.
+    """
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, n, size=(n_bumps, 2))
+    sigmas = rng.uniform(sigma_range[0], sigma_range[1], size=n_bumps)
+    amps = rng.uniform(amp_range[0], amp_range[1], size=n_bumps)
+    corner = rng.integers(0, n, size=2)
+
+    idx = np.arange(n, dtype=np.float64)
+    field = np.zeros((n, n), dtype=np.float64)
+    for (cx, cy), sg, a in zip(centres, sigmas, amps):
+        dx = idx - cx
+        dx = dx - n * np.round(dx / n)
+        dy = idx - cy
+        dy = dy - n * np.round(dy / n)
+        r2 = dy[:, None] ** 2 + dx[None, :] ** 2
+        field += a * np.exp(-r2 / (2.0 * sg * sg))
+    side = min(step_side, n)
+    xs = (corner[0] + np.arange(side)) % n
+    ys = (corner[1] + np.arange(side)) % n
+    field[np.ix_(ys, xs)] += 1.0
+    return field
+
+
+def shear_layer_macroscopic(n: int = 2048, seed: int = 0, u0: float = 0.05,
+                            kappa: float = 80.0, delta: float = 0.05):
+    """Double shear layer: returns ``(rho, ux, uy)``, each ``[n, n]`` float64.
+
+    Coordinates are cell centres ``x = (i + 1/2) / n``.  ``rho = 1``;
+    ``ux = u0 tanh(kappa (y - 1/4))`` for ``y <= 1/2`` and
+    ``u0 tanh(kappa (3/4 - y))`` above; ``uy = delta u0 sin(2 pi (x + phi))``
+    with the phase ``phi`` the single uniform ``[0, 1)`` draw of the seed.
+    ``u0`` is in lattice units (0.05 keeps the Mach number near 0.09).
+    """
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0.0, 1.0)
+    c = (np.arange(n, dtype=np.float64) + 0.5) / n
+    y = c[:, None]
+    x = c[None, :]
+    ux_col = np.where(c <= 0.5, u0 * np.tanh(kappa * (c - 0.25)),
+                      u0 * np.tanh(kappa * (0.75 - c)))
+    ux = np.broadcast_to(ux_col[:, None], (n, n)).copy()
+    uy = np.broadcast_to(delta * u0 * np.sin(2.0 * math.pi * (x + phi)), (n, n)).copy()
+    rho = np.ones((n, n), dtype=np.float64)
+    del y
+    return rho, ux, uy
+
+
+def taylor_green_macroscopic(n: int, u0: float = 0.02, rho0: float = 1.0):
+    """Periodic 2-D Taylor-Green vortex at t = 0 (no random draw).
+
+    ``ux = -u0 cos(kx) sin(ky)``, ``uy = u0 sin(kx) cos(ky)`` with
+    ``k = 2 pi / n`` on node coordinates ``x, y = i`` (lattice units), and the
+    incompressible pressure folded into the density
+    ``rho = rho0 - (3 rho0 u0^2 / 4)(cos 2kx + cos 2ky)`` (``c_s^2 = 1/3``).
+    """
+    k = 2.0 * math.pi / n
+    i = np.arange(n, dtype=np.float64)
+    x = i[None, :]
+    y = i[:, None]
+    ux = -u0 * np.cos(k * x) * np.sin(k * y)
+    uy = u0 * np.sin(k * x) * np.cos(k * y)
+    rho = rho0 - 0.75 * rho0 * u0 * u0 * (np.cos(2 * k * x) + np.cos(2 * k * y))
+    return rho, ux, uy
+
+
+def worked_example_field(n: int = 129) -> np.ndarray:
+    """The discontinuous 2-D test function of the compression section, ``[n, n]``.
+
+    ``f(x, y) = exp(x - y) sin(2 pi (x + y)) * step(y - x^2)`` with
+    ``step(s) = 1`` for ``s >= 0`` and 2 otherwise, sampled on the nodes
+    ``x_i = i / n``, ``i = 0 .. n-1`` (indexed ``[y, x]``).
+    """
+    c = np.arange(n, dtype=np.float64) / n
+    x = c[None, :]
+    y = c[:, None]
+    step = np.where(y - x * x >= 0.0, 1.0, 2.0)
+    return np.exp(x - y) * np.sin(2.0 * math.pi * (x + y)) * step
+
+
+def random_signal(shape, seed: int = 0, dtype=np.float64) -> np.ndarray:
+    """Standard-normal samples of the given shape and dtype."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(size=shape).astype(dtype)
+
+
+def random_coefficient_tiles(shape, seed: int = 0, dtype=np.float32,
+                             zero_frac: float = 0.3, scale_spread: float = 6.0) -> np.ndarray:
+    """Random coefficient-like values with exact zeros and a wide magnitude range.
+
+    Draw order: magnitudes ``10**U(-scale_spread, 0)``, signs from a fair coin,
+    then a Bernoulli(``zero_frac``) mask of exact zeros.  About 1% of the zeros
+    are made negative zero, which must behave as zero.
+    """
+    rng = np.random.default_rng(seed)
+    mag = 10.0 ** rng.uniform(-scale_spread, 0.0, size=shape)
+    sign = np.where(rng.integers(0, 2, size=shape) == 0, -1.0, 1.0)
+    zero = rng.uniform(0.0, 1.0, size=shape) < zero_frac
+    negz = rng.uniform(0.0, 1.0, size=shape) < 0.01
+    out = (sign * mag).astype(dtype)
+    out[zero] = 0.0
+    out[zero & negz] = -0.0
+    return out

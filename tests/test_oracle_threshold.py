@@ -1,0 +1,141 @@
+"""Pins of thresholding and compaction in the oracle.
+
+* the worked example of Section 2.1.2 (481 non-null coefficients out of 16641
+  with the constant rule at 0.2, 6 levels, 129 x 129), which also pins the 2-D
+  decomposition order (rows then columns), the detail classification and the
+  count of exact zeros;
+* masses equal before and after thresholding, even with all details dropped;
+* structural properties of the three rules of Section 2.2;
+* the record encoding against a brute-force ``np.flatnonzero``.
+"""
+import numpy as np
+import pytest
+
+from oracle import lbmz_oracle as O
+from synth import random_coefficient_tiles, worked_example_field
+
+
+def _golden_kv(golden):
+    return dict(ln.split() for ln in golden("worked_example.txt"))
+
+
+def test_worked_example_481_nonzeros(golden):
+    kv = _golden_kv(golden)
+    n, L, thr = int(kv["grid"]), int(kv["levels"]), float(kv["threshold"])
+    f = worked_example_field(n)
+    c = O.forward_2d(f, L, O.BL53)
+    t = O.threshold_table(n, L, thr, O.RULE_CONSTANT, np.float64)
+    ct = O.hard_threshold(c, t)
+    assert ct.size == int(kv["total"])
+    assert np.count_nonzero(ct) == int(kv["nonzero"])
+    # the same count in single precision
+    c32 = O.forward_2d(f.astype(np.float32), L, O.BL53)
+    t32 = O.threshold_table(n, L, thr, O.RULE_CONSTANT, np.float32)
+    assert np.count_nonzero(O.hard_threshold(c32, t32)) == int(kv["nonzero"])
+
+
+def test_worked_example_mass_conserved(golden):
+    kv = _golden_kv(golden)
+    n, L, thr = int(kv["grid"]), int(kv["levels"]), float(kv["threshold"])
+    f = worked_example_field(n)
+    w = np.ones(n)
+    w[0] = w[-1] = 0.5
+    w2 = w[:, None] * w[None, :]
+    c = O.forward_2d(f, L, O.BL53)
+    for t in (O.threshold_table(n, L, thr, O.RULE_CONSTANT, np.float64),
+              O.threshold_table(n, L, np.inf, O.RULE_CONSTANT, np.float64)):
+        r = O.inverse_2d(O.hard_threshold(c, t), L, O.BL53)
+        assert abs((r * w2).sum() - (f * w2).sum()) <= 1e-12 * np.abs(f).sum()
+
+
+def test_rules_coincide_with_one_level():
+    for rule in (O.RULE_CAPPED, O.RULE_ACCUM):
+        assert np.array_equal(O.threshold_table(65, 1, 1e-3, rule, np.float64),
+                              O.threshold_table(65, 1, 1e-3, O.RULE_CONSTANT, np.float64))
+
+
+def test_rule_ordering_and_coarsest_value():
+    s, L, eps = 65, 5, 1e-4
+    con = O.threshold_table(s, L, eps, O.RULE_CONSTANT, np.float64)
+    cap = O.threshold_table(s, L, eps, O.RULE_CAPPED, np.float64)
+    acc = O.threshold_table(s, L, eps, O.RULE_ACCUM, np.float64)
+    assert np.all(con <= cap) and np.all(cap <= acc)
+    lev = O.index_levels(s, L)
+    # samples are never thresholded
+    samp = (lev[:, None] == 0) & (lev[None, :] == 0)
+    assert np.all(con[samp] == 0) and np.all(cap[samp] == 0) and np.all(acc[samp] == 0)
+    # the coarsest detail (level L in x, sample in y) gets exactly eps
+    x = 1 << (L - 1)
+    assert cap[0, x] == eps and acc[0, x] == eps
+    # the finest detail in both dims gets eps 2^(L-1) (capped) and eps 2^(2L-2) (accumulated)
+    assert cap[1, 1] == eps * 2 ** (L - 1)
+    assert acc[1, 1] == eps * 2 ** (2 * L - 2)
+
+
+def test_threshold_is_strict_and_samples_survive():
+    s, L = 9, 2
+    c = np.full((s, s), 0.5)
+    t = O.threshold_table(s, L, 0.5, O.RULE_CONSTANT, np.float64)
+    out = O.hard_threshold(c, t)
+    assert np.array_equal(out, c)                   # |c| == thr is kept
+    t2 = O.threshold_table(s, L, 0.75, O.RULE_CONSTANT, np.float64)
+    out2 = O.hard_threshold(c, t2)
+    lev = O.index_levels(s, L)
+    samp = (lev[:, None] == 0) & (lev[None, :] == 0)
+    assert np.all(out2[samp] == 0.5) and np.all(out2[~samp] == 0)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_record_roundtrip_and_brute_force(dtype):
+    tiles = random_coefficient_tiles((6, 65, 65), seed=3, dtype=dtype, zero_frac=0.3)
+    # vary density across the encoding switch (2 nnz < 8 W  <=>  nnz < 4 W = 268)
+    tiles[1] = 0
+    tiles[2] = 0
+    tiles[2].reshape(-1)[[0, 64, 65, 4224]] = 1.5
+    tiles[3] = 0
+    tiles[3].reshape(-1)[:267] = 2.0
+    tiles[4] = 0
+    tiles[4].reshape(-1)[:268] = -3.0
+    tiles[5].reshape(-1)[17] = np.nan
+    for t in tiles:
+        flat = t.reshape(-1)
+        rec = O.encode_record(flat)
+        nnz = int(np.count_nonzero(flat != 0))
+        is_mask, vb, mb, rb = O.record_layout(nnz, flat.size, np.dtype(dtype).itemsize)
+        assert len(rec) == rb and rb % 16 == 0
+        assert is_mask == (nnz >= 268)
+        word = nnz | (O.MASK_BIT if is_mask else 0)
+        back = O.decode_record(rec, 0, word, flat.size, dtype)
+        keep = np.flatnonzero(flat != 0)             # brute force
+        assert np.array_equal(np.flatnonzero(back != 0) if not np.isnan(flat).any()
+                              else np.flatnonzero((back != 0) | np.isnan(back)), keep)
+        assert np.array_equal(back[keep], flat[keep], equal_nan=True)
+        vals = np.frombuffer(rec, dtype=dtype, count=nnz)
+        assert np.array_equal(vals, flat[keep], equal_nan=True)
+        if not is_mask:
+            idx = np.frombuffer(rec, dtype="<u2", count=nnz, offset=vb)
+            assert np.array_equal(idx, keep)
+        assert all(b == 0 for b in rec[nnz * np.dtype(dtype).itemsize:vb])
+
+
+def test_negative_zero_is_not_stored():
+    flat = np.zeros(65 * 65, dtype=np.float32)
+    flat[5] = -0.0
+    flat[6] = 1.0
+    rec = O.encode_record(flat)
+    assert len(rec) == 16                            # one value + one u16 index, padded
+    assert np.frombuffer(rec, dtype="<u2", count=1, offset=8)[0] == 6
+
+
+def test_store_placement_is_serial_prefix():
+    tiles = random_coefficient_tiles((4, 2, 33, 33), seed=9, dtype=np.float64, zero_frac=0.9)
+    table, pool = O.encode_store(tiles)
+    off = 0
+    for q in range(4):
+        for f in range(2):
+            assert table[q, f, 0] * 16 == off
+            nnz = int(table[q, f, 1]) & (O.MASK_BIT - 1)
+            off += O.record_layout(nnz, 33 * 33, 8)[3]
+    assert off == len(pool)
+    assert np.array_equal(O.decode_store(table, pool, 33, np.float64), tiles)
+    assert O.store_bytes(table, 33, 8) == len(pool) + table.size * 4
