@@ -1,0 +1,213 @@
+/*
+ * lbmz.h -- DWT-compressed stencil simulation on one AMD Instinct GPU (gfx950).
+ *
+ * C99 ABI of the library liblbmz.so.  The library keeps a regular-grid
+ * finite-volume or lattice-Boltzmann state in compressed form and advances it
+ * patch by patch: every patch is rebuilt from its thresholded wavelet
+ * coefficients by the inverse transform, completed with a one-node ghost ring
+ * taken from its neighbours, advanced by the stencil update, transformed
+ * forward, hard-thresholded, and its surviving coefficients are compacted back
+ * into the store.  This is the patch-at-a-time residency the paper proposes in
+ * its Introduction (Flint & Helluy, arXiv 2302.09883) and leaves as future
+ * work in its Conclusions; its compression pipeline is Section 2 (wavelet
+ * transform 2.1, thresholding 2.2, lossless stage 2.3) and its subgrid
+ * structure is Section 3.1.1.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an lbmz_status; on failure lbmz_last_error() gives a
+ *     per-context message.  No call throws or aborts.
+ *   - Ownership: the library owns every device allocation it makes (pools,
+ *     offset tables, halo strips, scratch).  Buffers passed in belong to the
+ *     caller and are only read or written during the call.
+ *   - Host buffers are used synchronously: the call returns after the copy on
+ *     the context's stream has completed.  Device buffers (flag *_on_device)
+ *     must live on the context's device and are used in stream order.
+ *   - Dense fields are n[0] x n[1] elements, x fastest (element (x, y) at
+ *     x + n[0] * y), unique cells only, in the scheme's dtype.
+ *   - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef LBMZ_H
+#define LBMZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbmz_ctx lbmz_ctx;
+
+typedef enum {
+  LBMZ_OK = 0,
+  LBMZ_EINVAL = -1,    /* invalid argument or geometry */
+  LBMZ_ENOMEM = -2,    /* device or host allocation failed */
+  LBMZ_EDEVICE = -3,   /* HIP runtime error */
+  LBMZ_EOVERFLOW = -4, /* pool could not be grown to hold the store */
+  LBMZ_ENAN = -5,      /* a non-finite coefficient appeared; state kept at the last good step */
+  LBMZ_ESTATE = -6     /* call not valid in the context's current state */
+} lbmz_status;
+
+typedef enum { LBMZ_F32 = 0, LBMZ_F64 = 1 } lbmz_dtype;
+
+/* Periodic regular grid of n[0] x n[1] cells of size h (Section 1, the
+ * periodicity condition).  dim must be 2; periodic must be 1; n[2] is ignored. */
+typedef struct {
+  int dim;
+  int64_t n[3];
+  int periodic;
+  double h;
+} lbmz_grid;
+
+typedef enum {
+  /* Finite-volume scheme of equation "vf_scheme" with the upwind transport
+   * flux of equation "upwind_trans": one scalar field, velocity vel[0..1],
+   * time step dt = cfl * h / max(|vel[0]|, |vel[1]|). */
+  LBMZ_FV_UPWIND = 0,
+  /* D2Q9 lattice-Boltzmann BGK (the paper names LBM and cites the textbook
+   * scheme): 9 populations with velocities (0,0) (1,0) (0,1) (-1,0) (0,-1)
+   * (1,1) (-1,1) (-1,-1) (1,-1), weights 4/9, 1/9, 1/36; pull streaming then
+   * collision with relaxation time tau; the stored state is post-collision. */
+  LBMZ_LBM_D2Q9_BGK = 1
+} lbmz_scheme_kind;
+
+typedef struct {
+  lbmz_scheme_kind kind;
+  lbmz_dtype dtype;   /* arithmetic and storage type of the state */
+  double vel[3];      /* FV: transport velocity (alpha, beta) */
+  double cfl;         /* FV: Courant number */
+  double tau;         /* LBM: relaxation time (> 1/2) */
+} lbmz_scheme;
+
+typedef enum {
+  /* Haar lifting on 2^J nodes per patch (d = b - a, s = a + d/2); patches
+   * partition the grid.  Not in the paper; used by the transport workload. */
+  LBMZ_HAAR = 0,
+  /* Folded BL5/3 lifting on 2^J + 1 nodes per patch (Section 2.1.2): the
+   * bordering node is shared with the neighbour (Section 3.1.1), which keeps
+   * the trapezoid mass of the grid exactly conserved. */
+  LBMZ_BL53 = 1
+} lbmz_wavelet;
+
+/* Section 2.2.  A detail of level lev (1 = finest) in an L-level transform
+ * has rank r = L - lev per dimension (0 = coarsest detail, a sample dimension
+ * counts 0).  Threshold: constant eps; capped eps * 2^max(r); accumulation
+ * eps * 2^sum(r).  A detail with |c| < threshold is set to zero; samples are
+ * never thresholded. */
+typedef enum { LBMZ_THR_CAPPED = 0, LBMZ_THR_CONSTANT = 1, LBMZ_THR_ACCUM = 2 } lbmz_thr_rule;
+
+/* Patch decomposition: p[0] = p[1] = cells per patch side, a power of two
+ * in {8, 16, 32, 64} dividing n.  p[2] is ignored. */
+typedef struct {
+  int p[3];
+  lbmz_wavelet wavelet;
+  lbmz_thr_rule rule;
+} lbmz_patch;
+
+typedef struct {
+  int64_t steps;          /* steps taken since the state was last set */
+  int64_t nnz_total;      /* stored coefficients over all records */
+  int64_t store_bytes;    /* record bytes + offset-table bytes of the current store */
+  int64_t capacity_bytes; /* bytes allocated for one pool buffer */
+  int64_t dense_bytes;    /* n[0] * n[1] * fields * sizeof(dtype) */
+  double ratio;           /* dense_bytes / store_bytes */
+  int32_t nfields;        /* 1 (FV) or 9 (LBM) */
+  int32_t npatch;         /* patches in the grid */
+  double totals[16];      /* FP64 per-field sums of the decompressed state: trapezoid
+                             weights 1/2 on shared bordering nodes (bl53), else 1 */
+  int64_t regrows;        /* pool regrowths absorbed since creation */
+  int64_t mask_records;   /* records stored as a bitmask */
+  int64_t list_records;   /* records stored as an index list */
+  double ms_last_call;    /* GPU time of the last lbmz_step call (HIP events) */
+} lbmz_stats_t;
+
+/* Create a compressed context (the method).  levels: wavelet levels L per
+ * dimension, 0 <= L <= J - 1 (bl53) or J (Haar) for patches of 2^J cells
+ * (one more bl53 level would have no update step and would not conserve
+ * mass).  eps >= 0 is the threshold constant c of Section 2.2.  The state is
+ * zero until lbmz_set_field / lbmz_set_macroscopic.  On success *out owns a
+ * new context.  Errors: LBMZ_EINVAL (geometry, levels, dtype/patch size
+ * without a compiled kernel, LDS limit), LBMZ_EDEVICE, LBMZ_ENOMEM. */
+int lbmz_create(const lbmz_grid* grid, const lbmz_scheme* scheme, const lbmz_patch* patch,
+                int levels, double eps, lbmz_ctx** out);
+
+/* Create an uncompressed context for the same grid and scheme: the plain
+ * two-buffer time loop of Section 1 on dense fields.  The same calls apply;
+ * lbmz_stats reports store_bytes = dense_bytes. */
+int lbmz_create_reference(const lbmz_grid* grid, const lbmz_scheme* scheme, lbmz_ctx** out);
+
+/* Route the context's device allocations through a caller allocator (e.g. a
+ * PyTorch caching allocator).  Must be called before the first allocation
+ * (right after create).  alloc returns NULL on failure. */
+int lbmz_set_allocator(lbmz_ctx* ctx, void* (*alloc)(size_t bytes, void* user),
+                       void (*free_)(void* ptr, void* user), void* user);
+
+/* Run all work of the context on the given hipStream_t (NULL = default stream). */
+int lbmz_set_stream(lbmz_ctx* ctx, void* hip_stream);
+
+/* Bytes of one pool buffer (two are kept: step input and step output).  The
+ * pool grows by itself when a step needs more (counted in regrows).  Default:
+ * one quarter of the worst-case store. */
+int lbmz_set_pool_capacity(lbmz_ctx* ctx, int64_t bytes);
+
+/* Set field `field` (0 <= field < nfields) of the state from a dense array of
+ * `bytes` = n[0] * n[1] * sizeof(dtype) bytes.  Other fields keep their
+ * values.  The state is compressed before the next step. */
+int lbmz_set_field(lbmz_ctx* ctx, int field, const void* src, size_t bytes, int src_on_device);
+
+/* LBM only: set all populations to the equilibrium of the given density and
+ * velocity fields (each a dense n[0] x n[1] array of the dtype). */
+int lbmz_set_macroscopic(lbmz_ctx* ctx, const void* rho, const void* ux, const void* uy,
+                         size_t bytes_each, int on_device);
+
+/* Advance n >= 0 steps.  One device-to-host read of the control block per
+ * call.  A pool overflow is absorbed by regrowing and replaying the
+ * remaining steps from the last good state; LBMZ_ENAN leaves the state at
+ * the last step whose coefficients were all finite. */
+int lbmz_step(lbmz_ctx* ctx, int n);
+
+/* Decompress field `field` of the current state into a dense array of
+ * n[0] * n[1] elements (the owned nodes of every patch). */
+int lbmz_decompress_field(lbmz_ctx* ctx, int field, void* dst, size_t bytes, int dst_on_device);
+
+int lbmz_stats(lbmz_ctx* ctx, lbmz_stats_t* out);
+
+/* ---- compressed store access (checkpoint, parity tests) -------------------
+ * Record layout of one (patch, field) tile of s x s coefficients, s = p + 1
+ * (bl53) or p (Haar), in-place interleaved wavelet layout, index t = x + s*y:
+ *   values of the non-zero coefficients in ascending t (dtype, little endian),
+ *   zero padding to a multiple of 8 bytes, then either nnz u16 indices t
+ *   (when 2 nnz < 8 W, W = ceil(s*s/64)) or W u64 mask words (bit t%64 of
+ *   word t/64), zero padding to a multiple of 16 bytes.
+ * Offset table: npatch * nfields entries of two u32, patch-major
+ *   (patch index px + (n/p) py), field-minor: record offset in 16-byte units
+ *   and nnz | (1u << 31 when the record is a bitmask).
+ * Record placement in the pool is not canonical (any non-overlapping layout
+ * is valid); the records themselves are. */
+
+/* Sizes of the current store: pool bytes in use and offset-table entries. */
+int lbmz_store_size(lbmz_ctx* ctx, int64_t* pool_bytes, int64_t* table_entries);
+
+/* Copy the current store to host buffers (table: 2 * table_entries u32). */
+int lbmz_get_store(lbmz_ctx* ctx, uint32_t* table_host, void* pool_host, size_t pool_bytes);
+
+/* Replace the state by a store given on the host; every record is validated
+ * on the host first (LBMZ_EINVAL on any inconsistency).  Halo strips and
+ * totals are rebuilt on the device. */
+int lbmz_put_store(lbmz_ctx* ctx, const uint32_t* table_host, const void* pool_host,
+                   size_t pool_bytes);
+
+/* Replace the state by given wavelet coefficient tiles [npatch][nfields][s][s]
+ * (dtype): the library thresholds and compacts them (the store's write path
+ * fed with known coefficients). */
+int lbmz_set_coefficients(lbmz_ctx* ctx, const void* coef, size_t bytes, int on_device);
+
+const char* lbmz_last_error(const lbmz_ctx* ctx);
+
+void lbmz_destroy(lbmz_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMZ_H */

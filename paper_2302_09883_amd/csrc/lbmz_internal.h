@@ -1,0 +1,90 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmz {
+
+enum Wavelet : int { W_HAAR = 0, W_BL53 = 1 };
+enum SchemeKind : int { S_FV = 0, S_LBM = 1 };
+enum Rule : int { R_CAPPED = 0, R_CONSTANT = 1, R_ACCUM = 2 };
+
+// Modes of the auxiliary (not time-critical) patch kernel.
+enum AuxMode : int {
+  AUX_INIT = 0,     // dense state -> forward transform -> threshold -> store
+  AUX_COEF = 1,     // given coefficient tiles -> threshold -> store
+  AUX_RESTORE = 2,  // store -> inverse transform -> halo strips + totals
+  AUX_DECOMP = 3    // store -> inverse transform -> dense state
+};
+
+// Control block in device memory, one per context.
+struct Ctrl {
+  unsigned long long top16[3];   // pool bump counters (16-byte units), rotated by epoch % 3
+  unsigned int abort;            // bit 0: pool overflow, bit 1: non-finite coefficient
+  unsigned int abort_epoch;      // smallest epoch that raised a flag (0xffffffff = none)
+};
+
+constexpr unsigned int ABORT_OVERFLOW = 1u;
+constexpr unsigned int ABORT_NONFINITE = 2u;
+constexpr uint32_t MASK_BIT = 0x80000000u;
+
+// Parameters of one patch-kernel launch.
+struct PatchArgs {
+  int n;             // grid cells per side
+  int npx;           // patches per side
+  int levels;        // wavelet levels per dimension
+  int rule;          // Rule
+  double eps;        // threshold constant
+  // scheme
+  double dt_over_h;  // FV
+  double cp[4];      // FV: max(a.N^k, 0)
+  double cm[4];      // FV: min(a.N^k, 0)
+  double omega;      // LBM: 1 / tau
+  // store, time n
+  const uint8_t* pool_in;
+  const uint32_t* table_in;
+  const void* halo_in;
+  // store, time n + 1
+  uint8_t* pool_out;
+  uint32_t* table_out;
+  void* halo_out;
+  double* partials_out;          // [npatch][nfields]
+  unsigned long long cap16;      // pool_out capacity in 16-byte units
+  Ctrl* ctrl;
+  unsigned int epoch;            // launch counter
+  // auxiliary modes
+  int mode;
+  const void* dense_in;          // AUX_INIT: [nfields][n][n]
+  const void* coef_in;           // AUX_COEF: [npatch][nfields][s][s]
+  void* dense_out;               // AUX_DECOMP: [nfields][n][n]
+};
+
+// Configuration key of a compiled kernel family.
+struct KernelKey {
+  int dtype;   // 0 = f32, 1 = f64
+  int p;       // cells per patch side
+  int wavelet; // Wavelet
+  int scheme;  // SchemeKind
+};
+
+// Launch the fused step kernel (time n -> n + 1) or the auxiliary kernel.
+// Return hipErrorInvalidValue when no kernel is compiled for the key.
+hipError_t launch_step(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s);
+hipError_t launch_aux(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s);
+bool have_kernel(const KernelKey& k);
+// LDS bytes used by the kernels of a key (0 if not compiled).
+size_t kernel_lds_bytes(const KernelKey& k);
+
+// Dense (uncompressed) reference step on a periodic [nfields][n][n] grid.
+hipError_t launch_reference_step(int dtype, int scheme, const void* in, void* out, int n,
+                                 const PatchArgs& a, hipStream_t s);
+// D2Q9 equilibrium populations [9][n][n] from rho, ux, uy [n][n].
+hipError_t launch_equilibrium(int dtype, const void* rho, const void* ux, const void* uy,
+                              void* f, int n, hipStream_t s);
+// Per-field trapezoid-free sums of a dense state into totals [nfields] (FP64,
+// fixed reduction order), for the reference context.
+hipError_t launch_dense_totals(int dtype, const void* in, int nfields, int n, double* partials,
+                               int nblocks, hipStream_t s);
+
+}  // namespace lbmz

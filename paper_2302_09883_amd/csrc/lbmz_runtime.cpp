@@ -1,0 +1,834 @@
+// Host runtime and C ABI of liblbmz (see include/lbmz.h).
+//
+// A context owns two copies of the compressed store (input and output of a
+// step: pool, offset table, halo strips, per-patch totals), a control block
+// for the pool bump counters and abort flags, and optional dense staging used
+// only while the state is being set.  lbmz_step issues one fused kernel per
+// time step and reads the control block once per call: a pool overflow is
+// absorbed by growing both pools and replaying the remaining steps from the
+// last good state; a non-finite coefficient stops at the last good state.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmz.h"
+#include "lbmz_internal.h"
+
+namespace lbmz {
+bool dispatch_f32_fv(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
+bool dispatch_f32_lbm(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
+bool dispatch_f64_fv(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
+bool dispatch_f64_lbm(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
+
+static bool dispatch(const KernelKey& k, int op, const PatchArgs* a, int npatch, hipStream_t s,
+                     hipError_t* err, size_t* lds) {
+  return dispatch_f32_fv(k, op, a, npatch, s, err, lds) || dispatch_f32_lbm(k, op, a, npatch, s, err, lds) ||
+         dispatch_f64_fv(k, op, a, npatch, s, err, lds) || dispatch_f64_lbm(k, op, a, npatch, s, err, lds);
+}
+
+hipError_t launch_step(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s) {
+  hipError_t e = hipErrorInvalidValue;
+  size_t lds = 0;
+  dispatch(k, 0, &a, npatch, s, &e, &lds);
+  return e;
+}
+
+hipError_t launch_aux(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s) {
+  hipError_t e = hipErrorInvalidValue;
+  size_t lds = 0;
+  dispatch(k, 1, &a, npatch, s, &e, &lds);
+  return e;
+}
+
+size_t kernel_lds_bytes(const KernelKey& k) {
+  hipError_t e = hipSuccess;
+  size_t lds = 0;
+  return dispatch(k, 2, nullptr, 0, nullptr, &e, &lds) ? lds : 0;
+}
+
+bool have_kernel(const KernelKey& k) { return kernel_lds_bytes(k) != 0; }
+}  // namespace lbmz
+
+using namespace lbmz;
+
+struct lbmz_ctx {
+  bool reference = false;
+  int dtype = 0;
+  size_t esize = 4;
+  int n = 0, p = 0, npx = 0, npatch = 0, s = 0, levels = 0, wavelet = 0, rule = 0, scheme = 0;
+  int nfields = 1, nslot = 1;
+  double eps = 0.0;
+  KernelKey key{};
+  PatchArgs base{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* (*ualloc)(size_t, void*) = nullptr;
+  void (*ufree)(void*, void*) = nullptr;
+  void* uuser = nullptr;
+  bool allocated = false;
+  // compressed store, double buffered
+  uint8_t* pool[2] = {nullptr, nullptr};
+  uint32_t* table[2] = {nullptr, nullptr};
+  void* halo[2] = {nullptr, nullptr};
+  double* partials[2] = {nullptr, nullptr};
+  int64_t cap_bytes = 0;
+  Ctrl* ctrl = nullptr;
+  Ctrl* ctrl_host = nullptr;   // pinned
+  int cur = 0;
+  unsigned epoch_next = 1;
+  uint64_t used16 = 0;         // store size of the current state, 16-byte units
+  // dense buffers: staging (compressed context) or the state (reference context)
+  void* dense[2] = {nullptr, nullptr};
+  bool staging_dirty = false;
+  bool have_state = false;
+  int64_t steps = 0, regrows = 0;
+  double ms_last = 0.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int fail(lbmz_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(c, expr)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail((c), LBMZ_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int64_t ncoef(const lbmz_ctx* c) { return (int64_t)c->s * c->s; }
+int64_t nwords(const lbmz_ctx* c) { return (ncoef(c) + 63) / 64; }
+
+// Record bytes for nnz stored coefficients (layout of include/lbmz.h).
+int64_t record_bytes(const lbmz_ctx* c, int64_t nnz, bool* is_mask) {
+  const int64_t w = nwords(c);
+  const bool mask = !(2 * nnz < 8 * w);
+  if (is_mask) *is_mask = mask;
+  const int64_t vb = align_up(nnz * (int64_t)c->esize, 8);
+  return align_up(vb + (mask ? 8 * w : 2 * nnz), 16);
+}
+
+int64_t worst_store_bytes(const lbmz_ctx* c) {
+  return record_bytes(c, ncoef(c), nullptr) * c->nfields * c->npatch;
+}
+
+void* dalloc(lbmz_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (c->ualloc) return c->ualloc(bytes, c->uuser);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dfree(lbmz_ctx* c, void* p) {
+  if (!p) return;
+  if (c->ufree) c->ufree(p, c->uuser);
+  else (void)hipFree(p);
+}
+
+size_t dense_bytes(const lbmz_ctx* c) { return (size_t)c->n * c->n * c->nfields * c->esize; }
+size_t field_bytes(const lbmz_ctx* c) { return (size_t)c->n * c->n * c->esize; }
+
+int ensure_buffers(lbmz_ctx* c) {
+  if (c->allocated) return LBMZ_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (c->reference) {
+    for (int b = 0; b < 2; ++b) {
+      c->dense[b] = dalloc(c, dense_bytes(c));
+      if (!c->dense[b]) return fail(c, LBMZ_ENOMEM, "dense state allocation failed");
+      HIPCHK(c, hipMemsetAsync(c->dense[b], 0, dense_bytes(c), c->stream));
+    }
+    c->partials[0] = static_cast<double*>(dalloc(c, sizeof(double) * 256 * c->nfields));
+    if (!c->partials[0]) return fail(c, LBMZ_ENOMEM, "partials allocation failed");
+  } else {
+    if (c->cap_bytes <= 0) c->cap_bytes = align_up(std::max<int64_t>(worst_store_bytes(c) / 4, 4096), 256);
+    const size_t tb = sizeof(uint32_t) * 2 * (size_t)c->npatch * c->nfields;
+    const size_t hb = c->esize * 4 * (size_t)c->nslot * c->s * c->npatch;
+    const size_t pb = sizeof(double) * (size_t)c->npatch * c->nfields;
+    for (int b = 0; b < 2; ++b) {
+      c->pool[b] = static_cast<uint8_t*>(dalloc(c, (size_t)c->cap_bytes));
+      c->table[b] = static_cast<uint32_t*>(dalloc(c, tb));
+      c->halo[b] = dalloc(c, hb);
+      c->partials[b] = static_cast<double*>(dalloc(c, pb));
+      if (!c->pool[b] || !c->table[b] || !c->halo[b] || !c->partials[b])
+        return fail(c, LBMZ_ENOMEM, "store allocation failed");
+      HIPCHK(c, hipMemsetAsync(c->table[b], 0, tb, c->stream));
+      HIPCHK(c, hipMemsetAsync(c->halo[b], 0, hb, c->stream));
+      HIPCHK(c, hipMemsetAsync(c->partials[b], 0, pb, c->stream));
+    }
+    c->ctrl = static_cast<Ctrl*>(dalloc(c, sizeof(Ctrl)));
+    if (!c->ctrl) return fail(c, LBMZ_ENOMEM, "control block allocation failed");
+    HIPCHK(c, hipHostMalloc((void**)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault));
+    Ctrl z{};
+    z.abort_epoch = 0xffffffffu;
+    *c->ctrl_host = z;
+    HIPCHK(c, hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  HIPCHK(c, hipEventCreate(&c->ev0));
+  HIPCHK(c, hipEventCreate(&c->ev1));
+  c->allocated = true;
+  return LBMZ_OK;
+}
+
+int reset_ctrl(lbmz_ctx* c) {
+  Ctrl z{};
+  z.abort_epoch = 0xffffffffu;
+  *c->ctrl_host = z;
+  HIPCHK(c, hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBMZ_OK;
+}
+
+int read_ctrl(lbmz_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBMZ_OK;
+}
+
+// Grow both pools to `bytes`, keeping the current store.
+int regrow(lbmz_ctx* c, int64_t bytes) {
+  bytes = align_up(bytes, 256);
+  if (bytes / 16 >= (int64_t)0xffffffffLL) return fail(c, LBMZ_EOVERFLOW, "store larger than 64 GiB");
+  uint8_t* np[2] = {nullptr, nullptr};
+  for (int b = 0; b < 2; ++b) {
+    np[b] = static_cast<uint8_t*>(dalloc(c, (size_t)bytes));
+    if (!np[b]) {
+      for (int k = 0; k < b; ++k) dfree(c, np[k]);
+      return fail(c, LBMZ_EOVERFLOW, "pool regrow to %lld bytes failed", (long long)bytes);
+    }
+  }
+  if (c->used16 > 0)
+    HIPCHK(c, hipMemcpyAsync(np[c->cur], c->pool[c->cur], (size_t)c->used16 * 16, hipMemcpyDeviceToDevice,
+                             c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int b = 0; b < 2; ++b) {
+    dfree(c, c->pool[b]);
+    c->pool[b] = np[b];
+  }
+  c->cap_bytes = bytes;
+  return LBMZ_OK;
+}
+
+PatchArgs args_for(lbmz_ctx* c, int in, int out, unsigned epoch) {
+  PatchArgs a = c->base;
+  a.pool_in = c->pool[in];
+  a.table_in = c->table[in];
+  a.halo_in = c->halo[in];
+  a.pool_out = c->pool[out];
+  a.table_out = c->table[out];
+  a.halo_out = c->halo[out];
+  a.partials_out = c->partials[out];
+  a.cap16 = (unsigned long long)(c->cap_bytes / 16);
+  a.ctrl = c->ctrl;
+  a.epoch = epoch;
+  return a;
+}
+
+// Produce a new state with an auxiliary writing mode (AUX_INIT or AUX_COEF)
+// from `src` (dense state or coefficient tiles); retries after a pool overflow.
+int produce_state(lbmz_ctx* c, int mode, const void* src) {
+  for (int attempt = 0; attempt < 64; ++attempt) {
+    int rc = reset_ctrl(c);
+    if (rc) return rc;
+    const unsigned e = c->epoch_next++;
+    PatchArgs a = args_for(c, c->cur, c->cur ^ 1, e);
+    a.mode = mode;
+    if (mode == AUX_INIT) a.dense_in = src;
+    else a.coef_in = src;
+    HIPCHK(c, launch_aux(c->key, a, c->npatch, c->stream));
+    rc = read_ctrl(c);
+    if (rc) return rc;
+    const Ctrl& h = *c->ctrl_host;
+    if (h.abort & ABORT_NONFINITE) return fail(c, LBMZ_ENAN, "non-finite value in the state being set");
+    if (h.abort & ABORT_OVERFLOW) {
+      const int64_t need = (int64_t)h.top16[e % 3] * 16;
+      rc = regrow(c, std::max<int64_t>(2 * c->cap_bytes, need + need / 4));
+      if (rc) return rc;
+      c->regrows++;
+      continue;
+    }
+    c->cur ^= 1;
+    c->used16 = h.top16[e % 3];
+    c->have_state = true;
+    c->steps = 0;
+    return LBMZ_OK;
+  }
+  return fail(c, LBMZ_EOVERFLOW, "pool kept overflowing");
+}
+
+int commit(lbmz_ctx* c) {
+  if (c->reference || !c->staging_dirty) return LBMZ_OK;
+  int rc = produce_state(c, AUX_INIT, c->dense[0]);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  dfree(c, c->dense[0]);
+  c->dense[0] = nullptr;
+  c->staging_dirty = false;
+  return LBMZ_OK;
+}
+
+// Decompress every field of the current compressed state into dst [M][n][n].
+int decompress_all(lbmz_ctx* c, void* dst) {
+  PatchArgs a = args_for(c, c->cur, c->cur, 0);
+  a.mode = AUX_DECOMP;
+  a.dense_out = dst;
+  HIPCHK(c, launch_aux(c->key, a, c->npatch, c->stream));
+  return LBMZ_OK;
+}
+
+// Dense staging holding the current state (compressed context).
+int ensure_staging(lbmz_ctx* c, bool fill) {
+  if (c->dense[0]) return LBMZ_OK;
+  c->dense[0] = dalloc(c, dense_bytes(c));
+  if (!c->dense[0]) return fail(c, LBMZ_ENOMEM, "staging allocation failed");
+  if (fill && c->have_state) {
+    int rc = decompress_all(c, c->dense[0]);
+    if (rc) return rc;
+  } else {
+    HIPCHK(c, hipMemsetAsync(c->dense[0], 0, dense_bytes(c), c->stream));
+  }
+  return LBMZ_OK;
+}
+
+int copy_in(lbmz_ctx* c, void* dst, const void* src, size_t bytes, int on_device) {
+  HIPCHK(c, hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           c->stream));
+  if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBMZ_OK;
+}
+
+int validate_common(const lbmz_grid* g, const lbmz_scheme* sc, lbmz_ctx* c) {
+  if (!g || !sc) return fail(c, LBMZ_EINVAL, "null argument");
+  if (g->dim != 2) return fail(c, LBMZ_EINVAL, "only 2-D grids are supported (dim=%d)", g->dim);
+  if (!g->periodic) return fail(c, LBMZ_EINVAL, "only periodic grids are supported");
+  if (g->n[0] <= 0 || g->n[0] != g->n[1] || g->n[0] > (1 << 16))
+    return fail(c, LBMZ_EINVAL, "grid must be square with 0 < n <= 65536");
+  if (sc->dtype != LBMZ_F32 && sc->dtype != LBMZ_F64) return fail(c, LBMZ_EINVAL, "bad dtype");
+  if (sc->kind == LBMZ_FV_UPWIND) {
+    const double vmax = std::max(std::fabs(sc->vel[0]), std::fabs(sc->vel[1]));
+    if (!(vmax > 0.0) || !std::isfinite(vmax)) return fail(c, LBMZ_EINVAL, "FV velocity must be non-zero");
+    if (!(sc->cfl > 0.0) || !std::isfinite(sc->cfl)) return fail(c, LBMZ_EINVAL, "cfl must be > 0");
+  } else if (sc->kind == LBMZ_LBM_D2Q9_BGK) {
+    if (!(sc->tau > 0.5) || !std::isfinite(sc->tau)) return fail(c, LBMZ_EINVAL, "tau must be > 1/2");
+  } else {
+    return fail(c, LBMZ_EINVAL, "unknown scheme kind %d", (int)sc->kind);
+  }
+  c->n = (int)g->n[0];
+  c->dtype = sc->dtype == LBMZ_F64 ? 1 : 0;
+  c->esize = c->dtype ? 8 : 4;
+  c->scheme = sc->kind == LBMZ_LBM_D2Q9_BGK ? S_LBM : S_FV;
+  c->nfields = c->scheme == S_LBM ? 9 : 1;
+  c->nslot = c->scheme == S_LBM ? 3 : 1;
+  PatchArgs& a = c->base;
+  memset(&a, 0, sizeof a);
+  a.n = c->n;
+  if (c->scheme == S_FV) {
+    const double vmax = std::max(std::fabs(sc->vel[0]), std::fabs(sc->vel[1]));
+    a.dt_over_h = sc->cfl / vmax;
+    const double an[4] = {sc->vel[0], -sc->vel[0], sc->vel[1], -sc->vel[1]};
+    for (int k = 0; k < 4; ++k) {
+      a.cp[k] = std::max(an[k], 0.0);
+      a.cm[k] = std::min(an[k], 0.0);
+    }
+  } else {
+    a.omega = 1.0 / sc->tau;
+  }
+  HIPCHK(c, hipGetDevice(&c->device));
+  return LBMZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbmz_create(const lbmz_grid* grid, const lbmz_scheme* scheme, const lbmz_patch* patch, int levels,
+                double eps, lbmz_ctx** out) {
+  if (!out) return LBMZ_EINVAL;
+  *out = nullptr;
+  lbmz_ctx* c = new (std::nothrow) lbmz_ctx();
+  if (!c) return LBMZ_ENOMEM;
+  int rc = validate_common(grid, scheme, c);
+  if (rc == LBMZ_OK && !patch) rc = fail(c, LBMZ_EINVAL, "null patch");
+  if (rc == LBMZ_OK) {
+    const int p = patch->p[0];
+    if (patch->p[1] != p || !(p == 8 || p == 16 || p == 32 || p == 64))
+      rc = fail(c, LBMZ_EINVAL, "patch must be square with p in {8, 16, 32, 64}");
+    else if (c->n % p != 0)
+      rc = fail(c, LBMZ_EINVAL, "grid size %d is not a multiple of the patch size %d", c->n, p);
+    else if (patch->wavelet != LBMZ_HAAR && patch->wavelet != LBMZ_BL53)
+      rc = fail(c, LBMZ_EINVAL, "unknown wavelet");
+    else if (patch->rule != LBMZ_THR_CAPPED && patch->rule != LBMZ_THR_CONSTANT && patch->rule != LBMZ_THR_ACCUM)
+      rc = fail(c, LBMZ_EINVAL, "unknown threshold rule");
+    else if (!(eps >= 0.0) || !std::isfinite(eps))
+      rc = fail(c, LBMZ_EINVAL, "eps must be finite and >= 0");
+    if (rc == LBMZ_OK) {
+      int j = 0;
+      while ((1 << j) < p) ++j;
+      const int cap = patch->wavelet == LBMZ_BL53 ? j - 1 : j;
+      if (levels < 0 || levels > cap)
+        rc = fail(c, LBMZ_EINVAL, "levels=%d outside [0, %d] for this wavelet and patch size", levels, cap);
+      c->p = p;
+      c->npx = c->n / p;
+      c->npatch = c->npx * c->npx;
+      c->wavelet = patch->wavelet == LBMZ_BL53 ? W_BL53 : W_HAAR;
+      c->s = c->wavelet == W_BL53 ? p + 1 : p;
+      c->levels = levels;
+      c->rule = patch->rule == LBMZ_THR_CAPPED ? R_CAPPED : patch->rule == LBMZ_THR_ACCUM ? R_ACCUM : R_CONSTANT;
+      c->eps = eps;
+      c->key = KernelKey{c->dtype, p, c->wavelet, c->scheme};
+    }
+  }
+  if (rc == LBMZ_OK) {
+    const size_t lds = kernel_lds_bytes(c->key);
+    int maxlds = 0;
+    if (lds == 0) {
+      rc = fail(c, LBMZ_EINVAL, "no kernel compiled for this dtype / patch size / wavelet / scheme");
+    } else if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess) {
+      rc = fail(c, LBMZ_EDEVICE, "cannot query the LDS limit");
+    } else if ((size_t)maxlds < lds) {
+      rc = fail(c, LBMZ_EINVAL, "patch needs %zu bytes of LDS, device allows %d", lds, maxlds);
+    }
+  }
+  if (rc == LBMZ_OK) {
+    PatchArgs& a = c->base;
+    a.npx = c->npx;
+    a.levels = c->levels;
+    a.rule = c->rule;
+    a.eps = c->eps;
+  }
+  if (rc != LBMZ_OK) {
+    // the message is lost with the context; callers get the code only
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return LBMZ_OK;
+}
+
+int lbmz_create_reference(const lbmz_grid* grid, const lbmz_scheme* scheme, lbmz_ctx** out) {
+  if (!out) return LBMZ_EINVAL;
+  *out = nullptr;
+  lbmz_ctx* c = new (std::nothrow) lbmz_ctx();
+  if (!c) return LBMZ_ENOMEM;
+  c->reference = true;
+  int rc = validate_common(grid, scheme, c);
+  if (rc != LBMZ_OK) {
+    delete c;
+    return rc;
+  }
+  c->p = c->n;
+  c->npx = 1;
+  c->npatch = 1;
+  c->s = c->n;
+  c->have_state = true;
+  *out = c;
+  return LBMZ_OK;
+}
+
+int lbmz_set_allocator(lbmz_ctx* c, void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* user) {
+  if (!c) return LBMZ_EINVAL;
+  if (c->allocated) return fail(c, LBMZ_ESTATE, "allocator must be set before the first allocation");
+  if ((alloc == nullptr) != (free_ == nullptr)) return fail(c, LBMZ_EINVAL, "alloc and free go together");
+  c->ualloc = alloc;
+  c->ufree = free_;
+  c->uuser = user;
+  return LBMZ_OK;
+}
+
+int lbmz_set_stream(lbmz_ctx* c, void* hip_stream) {
+  if (!c) return LBMZ_EINVAL;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  return LBMZ_OK;
+}
+
+int lbmz_set_pool_capacity(lbmz_ctx* c, int64_t bytes) {
+  if (!c) return LBMZ_EINVAL;
+  if (c->reference) return LBMZ_OK;
+  if (bytes < 16) return fail(c, LBMZ_EINVAL, "capacity must be >= 16 bytes");
+  if (!c->allocated) {
+    c->cap_bytes = align_up(bytes, 16);
+    return LBMZ_OK;
+  }
+  if (c->have_state && bytes < (int64_t)c->used16 * 16)
+    return fail(c, LBMZ_EINVAL, "capacity below the current store size");
+  return regrow(c, bytes);
+}
+
+int lbmz_set_field(lbmz_ctx* c, int field, const void* src, size_t bytes, int src_on_device) {
+  if (!c || !src) return LBMZ_EINVAL;
+  if (field < 0 || field >= c->nfields) return fail(c, LBMZ_EINVAL, "field %d out of range", field);
+  if (bytes != field_bytes(c)) return fail(c, LBMZ_EINVAL, "expected %zu bytes, got %zu", field_bytes(c), bytes);
+  int rc = ensure_buffers(c);
+  if (rc) return rc;
+  if (c->reference) {
+    rc = copy_in(c, static_cast<uint8_t*>(c->dense[c->cur]) + field * field_bytes(c), src, bytes, src_on_device);
+    if (rc == LBMZ_OK) c->steps = 0;
+    return rc;
+  }
+  rc = ensure_staging(c, true);
+  if (rc) return rc;
+  rc = copy_in(c, static_cast<uint8_t*>(c->dense[0]) + field * field_bytes(c), src, bytes, src_on_device);
+  if (rc) return rc;
+  c->staging_dirty = true;
+  return LBMZ_OK;
+}
+
+int lbmz_set_macroscopic(lbmz_ctx* c, const void* rho, const void* ux, const void* uy, size_t bytes_each,
+                         int on_device) {
+  if (!c || !rho || !ux || !uy) return LBMZ_EINVAL;
+  if (c->scheme != S_LBM) return fail(c, LBMZ_EINVAL, "macroscopic set-up is for the LBM scheme");
+  if (bytes_each != field_bytes(c)) return fail(c, LBMZ_EINVAL, "expected %zu bytes per field", field_bytes(c));
+  int rc = ensure_buffers(c);
+  if (rc) return rc;
+  void* tmp = dalloc(c, 3 * bytes_each);
+  if (!tmp) return fail(c, LBMZ_ENOMEM, "temporary allocation failed");
+  uint8_t* t8 = static_cast<uint8_t*>(tmp);
+  rc = copy_in(c, t8, rho, bytes_each, on_device);
+  if (!rc) rc = copy_in(c, t8 + bytes_each, ux, bytes_each, on_device);
+  if (!rc) rc = copy_in(c, t8 + 2 * bytes_each, uy, bytes_each, on_device);
+  void* dst = nullptr;
+  if (!rc) {
+    if (c->reference) {
+      dst = c->dense[c->cur];
+    } else {
+      rc = ensure_staging(c, false);
+      dst = c->dense[0];
+    }
+  }
+  if (!rc) {
+    hipError_t e = launch_equilibrium(c->dtype, t8, t8 + bytes_each, t8 + 2 * bytes_each, dst, c->n, c->stream);
+    if (e != hipSuccess) rc = fail(c, LBMZ_EDEVICE, "equilibrium kernel: %s", hipGetErrorString(e));
+  }
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail(c, LBMZ_EDEVICE, "sync: %s", hipGetErrorString(e));
+  }
+  dfree(c, tmp);
+  if (rc) return rc;
+  if (c->reference) {
+    c->steps = 0;
+    return LBMZ_OK;
+  }
+  c->staging_dirty = true;
+  return commit(c);
+}
+
+int lbmz_step(lbmz_ctx* c, int n) {
+  if (!c) return LBMZ_EINVAL;
+  if (n < 0) return fail(c, LBMZ_EINVAL, "negative step count");
+  int rc = ensure_buffers(c);
+  if (rc) return rc;
+  rc = commit(c);
+  if (rc) return rc;
+  if (!c->reference && !c->have_state) {
+    rc = ensure_staging(c, false);
+    if (rc) return rc;
+    c->staging_dirty = true;
+    rc = commit(c);
+    if (rc) return rc;
+  }
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  if (c->reference) {
+    for (int k = 0; k < n; ++k) {
+      HIPCHK(c, launch_reference_step(c->dtype, c->scheme, c->dense[c->cur], c->dense[c->cur ^ 1], c->n, c->base,
+                                      c->stream));
+      c->cur ^= 1;
+    }
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    HIPCHK(c, hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->ms_last = ms;
+    c->steps += n;
+    return LBMZ_OK;
+  }
+  int remaining = n;
+  for (int attempt = 0; remaining > 0; ++attempt) {
+    if (attempt > 64) return fail(c, LBMZ_EOVERFLOW, "pool kept overflowing");
+    const unsigned e0 = c->epoch_next;
+    const int cur0 = c->cur;
+    for (int k = 0; k < remaining; ++k) {
+      const unsigned e = c->epoch_next++;
+      PatchArgs a = args_for(c, c->cur, c->cur ^ 1, e);
+      HIPCHK(c, launch_step(c->key, a, c->npatch, c->stream));
+      c->cur ^= 1;
+    }
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    rc = read_ctrl(c);
+    if (rc) return rc;
+    const Ctrl h = *c->ctrl_host;
+    if (h.abort == 0) {
+      c->used16 = h.top16[(c->epoch_next - 1) % 3];
+      c->steps += remaining;
+      remaining = 0;
+      break;
+    }
+    const int kbad = (int)(h.abort_epoch - e0);   // first failing step of this batch
+    c->cur = cur0 ^ (kbad & 1);
+    if (kbad > 0) c->used16 = h.top16[(h.abort_epoch - 1) % 3];
+    c->steps += kbad;
+    remaining -= kbad;
+    if (h.abort & ABORT_NONFINITE) {
+      reset_ctrl(c);
+      return fail(c, LBMZ_ENAN, "non-finite coefficient at step %lld; state kept at the previous step",
+                  (long long)c->steps + 1);
+    }
+    const int64_t need = (int64_t)h.top16[h.abort_epoch % 3] * 16;
+    rc = regrow(c, std::max<int64_t>(2 * c->cap_bytes, need + need / 4));
+    if (rc) return rc;
+    c->regrows++;
+    rc = reset_ctrl(c);
+    if (rc) return rc;
+  }
+  HIPCHK(c, hipEventSynchronize(c->ev1));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  c->ms_last = ms;
+  return LBMZ_OK;
+}
+
+int lbmz_decompress_field(lbmz_ctx* c, int field, void* dst, size_t bytes, int dst_on_device) {
+  if (!c || !dst) return LBMZ_EINVAL;
+  if (field < 0 || field >= c->nfields) return fail(c, LBMZ_EINVAL, "field %d out of range", field);
+  if (bytes != field_bytes(c)) return fail(c, LBMZ_EINVAL, "expected %zu bytes, got %zu", field_bytes(c), bytes);
+  int rc = ensure_buffers(c);
+  if (rc) return rc;
+  const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (c->reference) {
+    HIPCHK(c, hipMemcpyAsync(dst, static_cast<uint8_t*>(c->dense[c->cur]) + field * field_bytes(c), bytes, kind,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBMZ_OK;
+  }
+  rc = commit(c);
+  if (rc) return rc;
+  if (!c->have_state) {
+    HIPCHK(c, dst_on_device ? hipMemsetAsync(dst, 0, bytes, c->stream) : hipSuccess);
+    if (!dst_on_device) memset(dst, 0, bytes);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBMZ_OK;
+  }
+  void* tmp = dalloc(c, dense_bytes(c));
+  if (!tmp) return fail(c, LBMZ_ENOMEM, "decompression scratch allocation failed");
+  rc = decompress_all(c, tmp);
+  if (!rc) {
+    hipError_t e = hipMemcpyAsync(dst, static_cast<uint8_t*>(tmp) + field * field_bytes(c), bytes, kind, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail(c, LBMZ_EDEVICE, "decompress copy: %s", hipGetErrorString(e));
+  }
+  dfree(c, tmp);
+  return rc;
+}
+
+int lbmz_stats(lbmz_ctx* c, lbmz_stats_t* out) {
+  if (!c || !out) return LBMZ_EINVAL;
+  int rc = ensure_buffers(c);
+  if (rc) return rc;
+  rc = commit(c);
+  if (rc) return rc;
+  memset(out, 0, sizeof *out);
+  out->steps = c->steps;
+  out->dense_bytes = (int64_t)dense_bytes(c);
+  out->nfields = c->nfields;
+  out->npatch = c->npatch;
+  out->regrows = c->regrows;
+  out->ms_last_call = c->ms_last;
+  if (c->reference) {
+    const int nb = 256;
+    HIPCHK(c, launch_dense_totals(c->dtype, c->dense[c->cur], c->nfields, c->n, c->partials[0], nb, c->stream));
+    std::vector<double> part((size_t)nb * c->nfields);
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partials[0], part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int f = 0; f < c->nfields && f < 16; ++f) {
+      double s = 0.0;
+      for (int b = 0; b < nb; ++b) s += part[(size_t)f * nb + b];
+      out->totals[f] = s;
+    }
+    out->store_bytes = out->dense_bytes;
+    out->capacity_bytes = out->dense_bytes;
+    out->nnz_total = (int64_t)c->n * c->n * c->nfields;
+    out->ratio = 1.0;
+    return LBMZ_OK;
+  }
+  const size_t ne = (size_t)c->npatch * c->nfields;
+  std::vector<uint32_t> tab(2 * ne);
+  std::vector<double> part(ne);
+  if (c->have_state) {
+    HIPCHK(c, hipMemcpyAsync(tab.data(), c->table[c->cur], tab.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partials[c->cur], part.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  int64_t rec = 0;
+  for (size_t i = 0; i < ne; ++i) {
+    const int64_t nnz = tab[2 * i + 1] & ~MASK_BIT;
+    out->nnz_total += nnz;
+    bool mask = false;
+    rec += record_bytes(c, nnz, &mask);
+    if (tab[2 * i + 1] & MASK_BIT) out->mask_records++;
+    else out->list_records++;
+  }
+  for (int f = 0; f < c->nfields && f < 16; ++f) {
+    double s = 0.0;
+    for (int q = 0; q < c->npatch; ++q) s += part[(size_t)q * c->nfields + f];
+    out->totals[f] = s;
+  }
+  out->store_bytes = rec + (int64_t)(ne * 8);
+  out->capacity_bytes = c->cap_bytes;
+  out->ratio = (double)out->dense_bytes / (double)out->store_bytes;
+  return LBMZ_OK;
+}
+
+int lbmz_store_size(lbmz_ctx* c, int64_t* pool_bytes, int64_t* table_entries) {
+  if (!c || !pool_bytes || !table_entries) return LBMZ_EINVAL;
+  if (c->reference) return fail(c, LBMZ_ESTATE, "a reference context has no compressed store");
+  int rc = ensure_buffers(c);
+  if (rc) return rc;
+  rc = commit(c);
+  if (rc) return rc;
+  *pool_bytes = (int64_t)c->used16 * 16;
+  *table_entries = (int64_t)c->npatch * c->nfields;
+  return LBMZ_OK;
+}
+
+int lbmz_get_store(lbmz_ctx* c, uint32_t* table_host, void* pool_host, size_t pool_bytes) {
+  if (!c || !table_host || (!pool_host && pool_bytes)) return LBMZ_EINVAL;
+  int64_t pb = 0, te = 0;
+  int rc = lbmz_store_size(c, &pb, &te);
+  if (rc) return rc;
+  if ((int64_t)pool_bytes != pb) return fail(c, LBMZ_EINVAL, "pool buffer is %zu bytes, store is %lld", pool_bytes,
+                                             (long long)pb);
+  HIPCHK(c, hipMemcpyAsync(table_host, c->table[c->cur], (size_t)te * 8, hipMemcpyDeviceToHost, c->stream));
+  if (pb) HIPCHK(c, hipMemcpyAsync(pool_host, c->pool[c->cur], (size_t)pb, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBMZ_OK;
+}
+
+int lbmz_put_store(lbmz_ctx* c, const uint32_t* table_host, const void* pool_host, size_t pool_bytes) {
+  if (!c || !table_host || (!pool_host && pool_bytes)) return LBMZ_EINVAL;
+  if (c->reference) return fail(c, LBMZ_ESTATE, "a reference context has no compressed store");
+  if (pool_bytes % 16) return fail(c, LBMZ_EINVAL, "pool size must be a multiple of 16");
+  const size_t ne = (size_t)c->npatch * c->nfields;
+  const uint8_t* pool = static_cast<const uint8_t*>(pool_host);
+  const int64_t nc = ncoef(c), w = nwords(c);
+  for (size_t i = 0; i < ne; ++i) {
+    const uint64_t off = (uint64_t)table_host[2 * i] * 16;
+    const int64_t nnz = table_host[2 * i + 1] & ~MASK_BIT;
+    const bool tagged_mask = (table_host[2 * i + 1] & MASK_BIT) != 0;
+    bool mask = false;
+    if (nnz > nc) return fail(c, LBMZ_EINVAL, "record %zu: nnz %lld > %lld", i, (long long)nnz, (long long)nc);
+    const int64_t rb = record_bytes(c, nnz, &mask);
+    if (mask != tagged_mask) return fail(c, LBMZ_EINVAL, "record %zu: wrong encoding tag", i);
+    if (off + (uint64_t)rb > pool_bytes) return fail(c, LBMZ_EINVAL, "record %zu overruns the pool", i);
+    const int64_t vb = align_up(nnz * (int64_t)c->esize, 8);
+    if (mask) {
+      int64_t cnt = 0;
+      for (int64_t k = 0; k < w; ++k) {
+        uint64_t word;
+        memcpy(&word, pool + off + vb + 8 * k, 8);
+        const int64_t valid = std::min<int64_t>(64, nc - 64 * k);
+        if (valid < 64 && (word >> valid) != 0) return fail(c, LBMZ_EINVAL, "record %zu: bits past the tile", i);
+        cnt += __builtin_popcountll(word);
+      }
+      if (cnt != nnz) return fail(c, LBMZ_EINVAL, "record %zu: mask count %lld != nnz", i, (long long)cnt);
+    } else {
+      int64_t prev = -1;
+      for (int64_t k = 0; k < nnz; ++k) {
+        uint16_t t;
+        memcpy(&t, pool + off + vb + 2 * k, 2);
+        if ((int64_t)t <= prev || t >= nc) return fail(c, LBMZ_EINVAL, "record %zu: bad index list", i);
+        prev = t;
+      }
+    }
+  }
+  int rc = ensure_buffers(c);
+  if (rc) return rc;
+  if ((int64_t)pool_bytes > c->cap_bytes) {
+    c->used16 = 0;
+    rc = regrow(c, (int64_t)pool_bytes);
+    if (rc) return rc;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->table[c->cur], table_host, ne * 8, hipMemcpyHostToDevice, c->stream));
+  if (pool_bytes) HIPCHK(c, hipMemcpyAsync(c->pool[c->cur], pool_host, pool_bytes, hipMemcpyHostToDevice, c->stream));
+  PatchArgs a = args_for(c, c->cur, c->cur, 0);
+  a.mode = AUX_RESTORE;
+  HIPCHK(c, launch_aux(c->key, a, c->npatch, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->dense[0]) {
+    dfree(c, c->dense[0]);
+    c->dense[0] = nullptr;
+  }
+  c->staging_dirty = false;
+  c->used16 = pool_bytes / 16;
+  c->have_state = true;
+  c->steps = 0;
+  return LBMZ_OK;
+}
+
+int lbmz_set_coefficients(lbmz_ctx* c, const void* coef, size_t bytes, int on_device) {
+  if (!c || !coef) return LBMZ_EINVAL;
+  if (c->reference) return fail(c, LBMZ_ESTATE, "a reference context has no compressed store");
+  const size_t want = (size_t)c->npatch * c->nfields * ncoef(c) * c->esize;
+  if (bytes != want) return fail(c, LBMZ_EINVAL, "expected %zu bytes of coefficients, got %zu", want, bytes);
+  int rc = ensure_buffers(c);
+  if (rc) return rc;
+  const void* src = coef;
+  void* tmp = nullptr;
+  if (!on_device) {
+    tmp = dalloc(c, bytes);
+    if (!tmp) return fail(c, LBMZ_ENOMEM, "temporary allocation failed");
+    rc = copy_in(c, tmp, coef, bytes, 0);
+    src = tmp;
+  }
+  if (!rc) rc = produce_state(c, AUX_COEF, src);
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail(c, LBMZ_EDEVICE, "sync: %s", hipGetErrorString(e));
+  }
+  dfree(c, tmp);
+  if (!rc && c->dense[0]) {
+    dfree(c, c->dense[0]);
+    c->dense[0] = nullptr;
+    c->staging_dirty = false;
+  }
+  return rc;
+}
+
+const char* lbmz_last_error(const lbmz_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void lbmz_destroy(lbmz_ctx* c) {
+  if (!c) return;
+  if (c->allocated) (void)hipStreamSynchronize(c->stream);
+  for (int b = 0; b < 2; ++b) {
+    dfree(c, c->pool[b]);
+    dfree(c, c->table[b]);
+    dfree(c, c->halo[b]);
+    dfree(c, c->partials[b]);
+    dfree(c, c->dense[b]);
+  }
+  dfree(c, c->ctrl);
+  if (c->ctrl_host) (void)hipHostFree(c->ctrl_host);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+}  // extern "C"

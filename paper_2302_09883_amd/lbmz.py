@@ -1,0 +1,289 @@
+"""ctypes binding of liblbmz (include/lbmz.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts arguments
+(NumPy arrays on the host, PyTorch tensors on the device), passes the current
+PyTorch stream, and turns status codes into exceptions.  If the library has
+not been built the import of :func:`library` raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmz.so")
+
+LBMZ_OK, LBMZ_EINVAL, LBMZ_ENOMEM, LBMZ_EDEVICE, LBMZ_EOVERFLOW, LBMZ_ENAN, LBMZ_ESTATE = 0, -1, -2, -3, -4, -5, -6
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "ENAN", -6: "ESTATE"}
+
+SCHEMES = {"fv_upwind": 0, "d2q9_bgk": 1}
+WAVELETS = {"haar": 0, "bl53": 1}
+RULES = {"capped": 0, "constant": 1, "accum": 2}
+DTYPES = {"f32": 0, "f64": 1}
+NP_DTYPES = {"f32": np.float32, "f64": np.float64}
+MASK_BIT = 1 << 31
+
+
+class LbmzError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbmz {_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(ct.Structure):
+    _fields_ = [("dim", ct.c_int), ("n", ct.c_int64 * 3), ("periodic", ct.c_int), ("h", ct.c_double)]
+
+
+class Scheme(ct.Structure):
+    _fields_ = [("kind", ct.c_int), ("dtype", ct.c_int), ("vel", ct.c_double * 3), ("cfl", ct.c_double),
+                ("tau", ct.c_double)]
+
+
+class Patch(ct.Structure):
+    _fields_ = [("p", ct.c_int * 3), ("wavelet", ct.c_int), ("rule", ct.c_int)]
+
+
+class Stats(ct.Structure):
+    _fields_ = [("steps", ct.c_int64), ("nnz_total", ct.c_int64), ("store_bytes", ct.c_int64),
+                ("capacity_bytes", ct.c_int64), ("dense_bytes", ct.c_int64), ("ratio", ct.c_double),
+                ("nfields", ct.c_int32), ("npatch", ct.c_int32), ("totals", ct.c_double * 16),
+                ("regrows", ct.c_int64), ("mask_records", ct.c_int64), ("list_records", ct.c_int64),
+                ("ms_last_call", ct.c_double)]
+
+
+_ALLOC = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_void_p)
+_FREE = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p)
+
+_lib = None
+
+
+def library() -> ct.CDLL:
+    """Load liblbmz.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "or python -m paper_2302_09883_amd.build")
+    lib = ct.CDLL(LIB_PATH)
+    P = ct.POINTER
+    vp = ct.c_void_p
+    sig = {
+        "lbmz_create": ([P(Grid), P(Scheme), P(Patch), ct.c_int, ct.c_double, P(vp)], ct.c_int),
+        "lbmz_create_reference": ([P(Grid), P(Scheme), P(vp)], ct.c_int),
+        "lbmz_set_allocator": ([vp, _ALLOC, _FREE, vp], ct.c_int),
+        "lbmz_set_stream": ([vp, vp], ct.c_int),
+        "lbmz_set_pool_capacity": ([vp, ct.c_int64], ct.c_int),
+        "lbmz_set_field": ([vp, ct.c_int, vp, ct.c_size_t, ct.c_int], ct.c_int),
+        "lbmz_set_macroscopic": ([vp, vp, vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
+        "lbmz_step": ([vp, ct.c_int], ct.c_int),
+        "lbmz_decompress_field": ([vp, ct.c_int, vp, ct.c_size_t, ct.c_int], ct.c_int),
+        "lbmz_stats": ([vp, P(Stats)], ct.c_int),
+        "lbmz_store_size": ([vp, P(ct.c_int64), P(ct.c_int64)], ct.c_int),
+        "lbmz_get_store": ([vp, vp, vp, ct.c_size_t], ct.c_int),
+        "lbmz_put_store": ([vp, vp, vp, ct.c_size_t], ct.c_int),
+        "lbmz_set_coefficients": ([vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
+        "lbmz_last_error": ([vp], ct.c_char_p),
+        "lbmz_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _buffer(x, dtype):
+    """(pointer, nbytes, on_device, keepalive) of a NumPy array or a CUDA tensor."""
+    if _is_torch(x):
+        if not x.is_cuda:
+            x = x.numpy()
+        else:
+            if not x.is_contiguous():
+                raise ValueError("device tensors must be contiguous")
+            return ct.c_void_p(x.data_ptr()), x.numel() * x.element_size(), 1, x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return ct.c_void_p(a.ctypes.data), a.nbytes, 0, a
+
+
+class Context:
+    """One compressed (or, with ``reference=True``, uncompressed) simulation."""
+
+    def __init__(self, n: int, scheme: str = "d2q9_bgk", dtype: str = "f32", p: int = 64,
+                 wavelet: str = "bl53", levels: int = 5, eps: float = 1e-4, rule: str = "capped",
+                 vel=(1.0, 0.5), cfl: float = 0.5, tau: float = 0.6, reference: bool = False,
+                 stream=None, torch_allocator: bool = False, pool_capacity: int | None = None):
+        self._lib = library()
+        self.n, self.scheme, self.dtype, self.p = n, scheme, dtype, p
+        self.wavelet, self.levels, self.eps, self.rule = wavelet, levels, eps, rule
+        self.reference = reference
+        self.np_dtype = NP_DTYPES[dtype]
+        self.nfields = 9 if scheme == "d2q9_bgk" else 1
+        self.s = (p + 1 if wavelet == "bl53" else p) if not reference else n
+        g = Grid(2, (ct.c_int64 * 3)(n, n, 1), 1, 1.0 / n)
+        sc = Scheme(SCHEMES[scheme], DTYPES[dtype], (ct.c_double * 3)(vel[0], vel[1], 0.0), cfl, tau)
+        h = ct.c_void_p()
+        if reference:
+            rc = self._lib.lbmz_create_reference(ct.byref(g), ct.byref(sc), ct.byref(h))
+        else:
+            pt = Patch((ct.c_int * 3)(p, p, 1), WAVELETS[wavelet], RULES[rule])
+            rc = self._lib.lbmz_create(ct.byref(g), ct.byref(sc), ct.byref(pt), levels, eps, ct.byref(h))
+        if rc != LBMZ_OK:
+            raise LbmzError(rc, "create failed (invalid geometry, levels, scheme or no kernel for the key)")
+        self._h = h
+        self._cb = None
+        if torch_allocator:
+            self._use_torch_allocator()
+        if stream is None:
+            stream = _current_stream()
+        self._check(self._lib.lbmz_set_stream(self._h, ct.c_void_p(stream)))
+        if pool_capacity is not None:
+            self.set_pool_capacity(pool_capacity)
+
+    # -- plumbing -------------------------------------------------------------
+    def _check(self, rc):
+        if rc != LBMZ_OK:
+            msg = self._lib.lbmz_last_error(self._h)
+            raise LbmzError(rc, msg.decode() if msg else "")
+
+    def _use_torch_allocator(self):
+        import torch
+
+        dev = torch.cuda.current_device()
+
+        def _alloc(nbytes, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev)
+            except Exception:   # noqa: BLE001 - reported to the library as NULL
+                return None
+
+        def _free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._cb = (_ALLOC(_alloc), _FREE(_free))
+        self._check(self._lib.lbmz_set_allocator(self._h, self._cb[0], self._cb[1], None))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbmz_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # noqa: BLE001
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- state ----------------------------------------------------------------
+    def set_pool_capacity(self, nbytes: int):
+        self._check(self._lib.lbmz_set_pool_capacity(self._h, int(nbytes)))
+
+    def set_field(self, field: int, data):
+        ptr, nb, dev, keep = _buffer(data, self.np_dtype)
+        self._check(self._lib.lbmz_set_field(self._h, field, ptr, nb, dev))
+        del keep
+
+    def set_macroscopic(self, rho, ux, uy):
+        bufs = [_buffer(x, self.np_dtype) for x in (rho, ux, uy)]
+        if len({b[1] for b in bufs}) != 1 or len({b[2] for b in bufs}) != 1:
+            raise ValueError("rho, ux, uy must have the same size and location")
+        self._check(self._lib.lbmz_set_macroscopic(self._h, bufs[0][0], bufs[1][0], bufs[2][0], bufs[0][1],
+                                                   bufs[0][2]))
+
+    def set_coefficients(self, coef):
+        ptr, nb, dev, keep = _buffer(coef, self.np_dtype)
+        self._check(self._lib.lbmz_set_coefficients(self._h, ptr, nb, dev))
+        del keep
+
+    def step(self, n: int = 1):
+        self._check(self._lib.lbmz_step(self._h, int(n)))
+
+    def decompress_field(self, field: int, out=None):
+        if out is None:
+            out = np.empty((self.n, self.n), dtype=self.np_dtype)
+        ptr, nb, dev, keep = _buffer(out, self.np_dtype)
+        if not dev and keep is not out:
+            raise ValueError("host output must be a contiguous array of the context dtype")
+        self._check(self._lib.lbmz_decompress_field(self._h, field, ptr, nb, dev))
+        return out
+
+    def fields(self) -> np.ndarray:
+        """All fields on the host, ``[nfields, n, n]``."""
+        return np.stack([self.decompress_field(f) for f in range(self.nfields)])
+
+    def stats(self) -> dict:
+        st = Stats()
+        self._check(self._lib.lbmz_stats(self._h, ct.byref(st)))
+        d = {k: getattr(st, k) for k, _ in Stats._fields_}
+        d["totals"] = list(st.totals)[:self.nfields]
+        return d
+
+    # -- compressed store -------------------------------------------------------
+    def store(self):
+        """``(table uint32 [npatch, nfields, 2], pool bytes)`` of the current state."""
+        pb, te = ct.c_int64(), ct.c_int64()
+        self._check(self._lib.lbmz_store_size(self._h, ct.byref(pb), ct.byref(te)))
+        table = np.empty(2 * te.value, dtype=np.uint32)
+        pool = np.empty(pb.value, dtype=np.uint8)
+        self._check(self._lib.lbmz_get_store(self._h, ct.c_void_p(table.ctypes.data),
+                                             ct.c_void_p(pool.ctypes.data), pool.nbytes))
+        npatch = te.value // self.nfields
+        return table.reshape(npatch, self.nfields, 2), pool.tobytes()
+
+    def put_store(self, table, pool: bytes):
+        t = np.ascontiguousarray(table, dtype=np.uint32)
+        buf = np.frombuffer(pool, dtype=np.uint8)
+        self._check(self._lib.lbmz_put_store(self._h, ct.c_void_p(t.ctypes.data),
+                                             ct.c_void_p(buf.ctypes.data), buf.nbytes))
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:   # noqa: BLE001
+        pass
+    return None
+
+
+def decode_records(table: np.ndarray, pool: bytes, s: int, dtype) -> np.ndarray:
+    """Coefficient tiles ``[npatch, nfields, s, s]`` from a store (host-side reader).
+
+    Reads the record layout of include/lbmz.h; used to inspect what the
+    library wrote.
+    """
+    dtype = np.dtype(dtype)
+    npatch, nf = table.shape[:2]
+    nc = s * s
+    w = (nc + 63) // 64
+    out = np.zeros((npatch, nf, nc), dtype=dtype)
+    buf = np.frombuffer(pool, dtype=np.uint8)
+    for q in range(npatch):
+        for f in range(nf):
+            off = int(table[q, f, 0]) * 16
+            word = int(table[q, f, 1])
+            nnz = word & (MASK_BIT - 1)
+            vb = (nnz * dtype.itemsize + 7) // 8 * 8
+            vals = buf[off:off + nnz * dtype.itemsize].view(dtype)
+            if word & MASK_BIT:
+                words = buf[off + vb:off + vb + 8 * w].view("<u8")
+                bits = np.unpackbits(words.view(np.uint8), bitorder="little")[:nc].astype(bool)
+                out[q, f, bits] = vals
+            else:
+                idx = buf[off + vb:off + vb + 2 * nnz].view("<u2").astype(np.int64)
+                out[q, f, idx] = vals
+    return out.reshape(npatch, nf, s, s)

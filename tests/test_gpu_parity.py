@@ -1,0 +1,337 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars:
+* integer work (masks, index lists, nnz, encoding tags, record bytes) is
+  bit-exact when both sides get the same coefficients;
+* floating-point fields: float64 within 1e-12 relative to the field scale,
+  float32 within 1e-5 relative (the bar of the method's statement), with the
+  per-test bound derived in the test;
+* after a full step, keep/drop decisions may differ only for coefficients
+  whose magnitude lies within rounding distance of their threshold.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lbmz_oracle as O
+from synth import fv_gaussians_and_step, random_coefficient_tiles, random_signal, shear_layer_macroscopic
+
+from gpu_helpers import (borderline, gpu_coefficients, make_ctx, oracle_twin, records_of, require_gpu, torch)
+
+pytestmark = pytest.mark.gpu
+
+# (n, scheme, dtype, p, wavelet, levels)
+GEOMS = [
+    (128, "d2q9_bgk", "f32", 64, "bl53", 5),
+    (96, "d2q9_bgk", "f32", 32, "bl53", 4),
+    (64, "d2q9_bgk", "f32", 16, "haar", 4),
+    (64, "d2q9_bgk", "f64", 32, "bl53", 4),
+    (256, "fv_upwind", "f64", 32, "haar", 4),
+    (128, "fv_upwind", "f32", 64, "bl53", 5),
+    (64, "fv_upwind", "f64", 8, "bl53", 2),
+]
+
+
+def _say(*args):
+    print("[case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+def _initial_state(n, scheme, dtype, seed=0):
+    if scheme == "fv_upwind":
+        return fv_gaussians_and_step(n, seed=seed, step_side=max(4, n // 4))[None].astype(dtype)
+    rho, ux, uy = shear_layer_macroscopic(n, seed=seed, kappa=20.0)
+    return O.d2q9_equilibrium(rho, ux, uy).astype(dtype)
+
+
+def _set_state(ctx, state):
+    for f in range(state.shape[0]):
+        ctx.set_field(f, state[f])
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+@pytest.mark.parametrize("eps,rule,zero_frac", [(0.0, "capped", 0.3), (3e-3, "capped", 0.0),
+                                                (1e-2, "accum", 0.5), (5e-2, "constant", 0.9)])
+def test_compaction_bit_exact(geom, eps, rule, zero_frac):
+    n, scheme, dtype, p, wavelet, levels = geom
+    _say("compaction", geom, eps, rule)
+    ctx = make_ctx(n, scheme, dtype, p, wavelet, levels, eps, rule)
+    twin = oracle_twin(ctx)
+    g = twin.g
+    tiles = random_coefficient_tiles((g.npatch, ctx.nfields, g.s, g.s), seed=hash((n, p, rule)) % 1000,
+                                     dtype=ctx.np_dtype, zero_frac=zero_frac, scale_spread=5.0)
+    # make a few records sparse enough for the index-list encoding
+    tiles[0, 0] = 0
+    tiles[0, 0, 0, :3] = 1.25
+    ctx.set_coefficients(tiles)
+    want = O.hard_threshold(tiles, twin.thr)
+    table, pool = ctx.store()
+    for q in range(g.npatch):
+        for f in range(ctx.nfields):
+            rec = O.encode_record(np.ascontiguousarray(want[q, f]).reshape(-1))
+            nnz = int(np.count_nonzero(want[q, f] != 0))
+            is_mask = O.record_layout(nnz, g.s * g.s, np.dtype(ctx.np_dtype).itemsize)[0]
+            assert int(table[q, f, 1]) == nnz | (O.MASK_BIT if is_mask else 0), (q, f)
+            assert records_of(table, pool, q, f, ctx) == rec, (q, f)
+    # records tile the used pool without overlap
+    spans = sorted((int(table[q, f, 0]) * 16, len(records_of(table, pool, q, f, ctx)))
+                   for q in range(g.npatch) for f in range(ctx.nfields))
+    pos = 0
+    for off, ln in spans:
+        assert off == pos
+        pos += ln
+    assert pos == len(pool)
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+def test_decompress_matches_oracle_inverse(geom):
+    n, scheme, dtype, p, wavelet, levels = geom
+    _say("decompress", geom)
+    ctx = make_ctx(n, scheme, dtype, p, wavelet, levels, 1e-3)
+    twin = oracle_twin(ctx)
+    twin.set_grid(_initial_state(n, scheme, ctx.np_dtype))
+    table, pool = O.encode_store(twin.coef)
+    ctx.put_store(table, pool)
+    got = ctx.fields()
+    want = twin.grid()
+    tol = 1e-12 if dtype == "f64" else 2e-6
+    scale = np.max(np.abs(want))
+    assert np.max(np.abs(got - want)) <= tol * scale
+    # the store read back is the one written
+    t2, p2 = ctx.store()
+    assert np.array_equal(t2, table) and p2 == pool
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+def test_initial_compression_matches_oracle(geom):
+    n, scheme, dtype, p, wavelet, levels = geom
+    _say("init", geom)
+    ctx = make_ctx(n, scheme, dtype, p, wavelet, levels, 0.0)
+    twin = oracle_twin(ctx)
+    state = _initial_state(n, scheme, ctx.np_dtype)
+    _set_state(ctx, state)
+    twin.set_grid(state)
+    coef, table, _ = gpu_coefficients(ctx)
+    tol = 1e-12 if dtype == "f64" else 2e-6
+    scale = np.max(np.abs(state))
+    assert np.max(np.abs(coef - twin.coef)) <= tol * scale
+    # eps = 0 drops nothing: the decompressed state is the input (perfect reconstruction)
+    assert np.max(np.abs(ctx.fields() - state)) <= tol * scale
+    st = ctx.stats()
+    assert st["nnz_total"] == int(np.count_nonzero(coef))
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+@pytest.mark.parametrize("eps", [0.0, 1e-4, 1e-3])
+def test_one_step_from_common_state(geom, eps):
+    n, scheme, dtype, p, wavelet, levels = geom
+    _say("one-step", geom, eps)
+    ctx = make_ctx(n, scheme, dtype, p, wavelet, levels, eps)
+    twin = oracle_twin(ctx)
+    twin.set_grid(_initial_state(n, scheme, ctx.np_dtype, seed=3))
+    twin.step(2)
+    table, pool = O.encode_store(twin.coef)
+    ctx.put_store(table, pool)
+    ctx.step(1)
+    twin.step(1)
+    got, gt, _ = gpu_coefficients(ctx)
+    want = twin.coef
+    u = np.finfo(ctx.np_dtype).eps
+    scale = float(np.max(np.abs(twin.grid())))
+    delta = 256 * u * scale
+    thr = np.broadcast_to(twin.thr, want.shape)
+    kg, kw = got != 0, want != 0
+    flip = kg != kw
+    # raw coefficient before thresholding is not available; a flip must sit at the threshold
+    assert np.all(borderline(np.where(kg, got, want), thr, delta)[flip]), int(flip.sum())
+    both = kg & kw
+    assert np.max(np.abs(got[both] - want[both]), initial=0.0) <= delta
+    # the GPU's inverse transform of its own store equals the oracle's
+    lossy = O.assemble_grid(O.inverse_2d(got, ctx.levels, ctx.wavelet), twin.g)
+    assert np.max(np.abs(ctx.fields() - lossy)) <= 16 * u * scale
+
+
+def test_cfg1_full_run_against_oracle():
+    # transport workload: 256^2, 32^2 patches, Haar, float64, L = 4, eps = 1e-4, 100 steps
+    _say("cfg1 full")
+    n, steps = 256, 100
+    ctx = make_ctx(n, "fv_upwind", "f64", 32, "haar", 4, 1e-4)
+    twin = oracle_twin(ctx)
+    state = fv_gaussians_and_step(n, seed=0)[None]
+    _set_state(ctx, state)
+    twin.set_grid(state)
+    t0 = ctx.stats()["totals"][0]
+    ctx.step(steps)
+    twin.step(steps)
+    got = ctx.fields()
+    want = twin.grid()
+    st = ctx.stats()
+    # borderline keep/drop flips compound over 100 steps; the bound is a few thresholds
+    print("cfg1 max|gpu-oracle|", float(np.max(np.abs(got - want))), "store", st["store_bytes"],
+          twin.store_bytes(), flush=True)
+    # float64 on both sides: a keep/drop flip needs a coefficient within ~1e-13
+    # of its threshold, so the runs agree to round-off
+    assert np.max(np.abs(got - want)) <= 1e-10
+    assert st["store_bytes"] == twin.store_bytes()
+    assert abs(st["totals"][0] - t0) <= 1e-11 * abs(t0)
+    assert abs(st["totals"][0] - want.sum()) <= 1e-9 * abs(t0)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-4])
+def test_lbm_small_run_against_oracle(eps):
+    _say("lbm small run", eps)
+    n, steps = 128, 20
+    ctx = make_ctx(n, "d2q9_bgk", "f32", 64, "bl53", 5, eps)
+    twin = oracle_twin(ctx, dtype=np.float64)
+    state = _initial_state(n, "d2q9_bgk", np.float64)
+    _set_state(ctx, state.astype(np.float32))
+    twin.set_grid(state.astype(np.float32).astype(np.float64))
+    ctx.step(steps)
+    twin.step(steps)
+    got = ctx.fields()
+    want = twin.grid()
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    if eps == 0.0:
+        assert rel <= 1e-5
+    else:
+        assert rel <= 1e-4
+        # same number of stored coefficients up to borderline decisions (the
+        # oracle runs in float64 here, so compare counts, not bytes)
+        st = ctx.stats()
+        assert abs(st["nnz_total"] - int(twin.nnz().sum())) <= 0.02 * twin.nnz().sum() + 8
+
+
+@pytest.mark.parametrize("scheme,dtype", [("d2q9_bgk", "f32"), ("fv_upwind", "f64"), ("d2q9_bgk", "f64")])
+def test_reference_context_matches_oracle(scheme, dtype):
+    _say("reference", scheme, dtype)
+    n, steps = 64, 10
+    from paper_2302_09883_amd import Context
+    ref = Context(n, scheme=scheme, dtype=dtype, reference=True)
+    state = _initial_state(n, scheme, np.float64)
+    _set_state(ref, state.astype(ref.np_dtype))
+    ref.step(steps)
+    want = state.astype(ref.np_dtype).astype(np.float64)
+    sch = O.Scheme(scheme, vel=(1.0, 0.5), cfl=0.5, tau=0.6)
+    for _ in range(steps):
+        want = O.dense_step(want, sch)
+    tol = 1e-13 if dtype == "f64" else 1e-6
+    assert np.max(np.abs(ref.fields() - want)) <= tol * np.max(np.abs(want))
+
+
+def test_zero_threshold_equals_reference_run():
+    _say("eps0 vs reference")
+    n, steps = 256, 50
+    from paper_2302_09883_amd import Context
+    ctx = make_ctx(n, "d2q9_bgk", "f32", 64, "bl53", 5, 0.0)
+    ref = Context(n, scheme="d2q9_bgk", dtype="f32", reference=True)
+    rho, ux, uy = shear_layer_macroscopic(n, seed=1)
+    for c in (ctx, ref):
+        c.set_macroscopic(rho.astype(np.float32), ux.astype(np.float32), uy.astype(np.float32))
+        c.step(steps)
+    a, b = ctx.fields(), ref.fields()
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 1e-5
+
+
+@pytest.mark.parametrize("scheme,wavelet,dtype,p,levels", [("d2q9_bgk", "bl53", "f32", 64, 5),
+                                                           ("fv_upwind", "haar", "f64", 32, 4)])
+def test_conservation_of_totals(scheme, wavelet, dtype, p, levels):
+    _say("conservation", scheme, wavelet, dtype)
+    n = 256
+    ctx = make_ctx(n, scheme, dtype, p, wavelet, levels, 1e-3)
+    _set_state(ctx, _initial_state(n, scheme, ctx.np_dtype))
+    t0 = np.array(ctx.stats()["totals"])
+    ctx.step(30)
+    t1 = np.array(ctx.stats()["totals"])
+    tol = 1e-12 if dtype == "f64" else 2e-6
+    assert abs(t1.sum() - t0.sum()) <= tol * abs(t0.sum())
+    if scheme == "d2q9_bgk":
+        c = O.D2Q9_C
+        for ax in (0, 1):
+            assert abs((c[:, ax] * t1).sum() - (c[:, ax] * t0).sum()) <= tol * abs(t0.sum())
+    # totals agree with the decompressed state's unique-node sum
+    assert abs(ctx.fields().astype(np.float64).sum() - t1.sum()) <= tol * abs(t0.sum())
+
+
+def test_shared_faces_are_identical_on_gpu():
+    _say("shared faces")
+    n, p = 256, 64
+    ctx = make_ctx(n, "d2q9_bgk", "f32", p, "bl53", 5, 1e-4)
+    _set_state(ctx, _initial_state(n, "d2q9_bgk", np.float32))
+    ctx.step(5)
+    coef, _, _ = gpu_coefficients(ctx)
+    npx = n // p
+    for py in range(npx):
+        for px in range(npx):
+            q = px + npx * py
+            right = (px + 1) % npx + npx * py
+            up = px + npx * ((py + 1) % npx)
+            assert np.array_equal(coef[q, :, :, p], coef[right, :, :, 0])
+            assert np.array_equal(coef[q, :, p, :], coef[up, :, 0, :])
+
+
+def test_pool_overflow_regrow_is_transparent():
+    _say("overflow regrow")
+    n = 128
+    state = _initial_state(n, "d2q9_bgk", np.float32)
+    outs = []
+    for cap in (None, 16):
+        ctx = make_ctx(n, "d2q9_bgk", "f32", 64, "bl53", 5, 1e-4, pool_capacity=cap)
+        _set_state(ctx, state)
+        ctx.step(7)
+        outs.append((ctx.fields(), ctx.stats()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[1][1]["regrows"] >= 1
+    assert outs[0][1]["store_bytes"] == outs[1][1]["store_bytes"]
+
+
+def test_nonfinite_input_is_reported():
+    _say("nan input")
+    from paper_2302_09883_amd import LbmzError
+    n = 64
+    ctx = make_ctx(n, "fv_upwind", "f64", 32, "haar", 4, 1e-4)
+    w = fv_gaussians_and_step(n, seed=0, step_side=16)
+    w[5, 7] = np.nan
+    ctx.set_field(0, w)
+    with pytest.raises(LbmzError) as ei:
+        ctx.step(1)
+    assert ei.value.code == -5
+
+
+def test_invalid_arguments_are_rejected():
+    _say("invalid args")
+    from paper_2302_09883_amd import LbmzError
+    with pytest.raises(LbmzError):
+        make_ctx(128, "d2q9_bgk", "f32", 64, "bl53", 6, 1e-4)      # past the bl53 level cap
+    with pytest.raises(LbmzError):
+        make_ctx(100, "d2q9_bgk", "f32", 64, "bl53", 3, 1e-4)      # grid not a multiple of p
+    with pytest.raises(LbmzError):
+        make_ctx(128, "d2q9_bgk", "f64", 64, "bl53", 3, 1e-4)      # LDS: no such kernel
+    with pytest.raises(LbmzError):
+        make_ctx(128, "d2q9_bgk", "f32", 64, "bl53", 3, -1.0)      # negative threshold
+    ctx = make_ctx(64, "fv_upwind", "f64", 32, "haar", 4, 1e-4)
+    with pytest.raises(LbmzError):
+        ctx.set_field(1, np.zeros((64, 64)))
+    with pytest.raises(LbmzError):
+        ctx.set_field(0, np.zeros((32, 32)))
+
+
+def test_repeat_runs_are_identical():
+    _say("repeat determinism")
+    n = 256
+    state = _initial_state(n, "d2q9_bgk", np.float32)
+    res = []
+    for _ in range(2):
+        ctx = make_ctx(n, "d2q9_bgk", "f32", 64, "bl53", 5, 1e-4)
+        _set_state(ctx, state)
+        ctx.step(10)
+        coef, table, _ = gpu_coefficients(ctx)
+        res.append((coef, table[..., 1].copy(), ctx.stats()["totals"]))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    assert res[0][2] == res[1][2]
