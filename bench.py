@@ -1,0 +1,266 @@
+#!/usr/bin/env python
+"""Benchmark of the compressed patch loop on one MI355X.
+
+Workload (the lattice-Boltzmann configuration): D2Q9 BGK, tau = 0.6, float32
+populations, 2048 x 2048 periodic grid, 64 x 64 patches (1024 patches of
+65 x 65 shared-border tiles), folded BL5/3 wavelet with 5 levels, capped
+threshold, eps swept over {1e-5, 1e-4, 1e-3}; initial state: double shear
+layer at equilibrium (seed 0).  A "step" is one time step of the whole hot
+path over all patches: one launch of the fused patch kernel.
+
+Printed: one JSON line with MLUPS at the primary eps (1e-4) including the
+decompression and recompression, the sweep's compression ratios and errors
+against the uncompressed run of the same length, the compression ratio at a
+fixed relative L2 error, a roofline object for the fused kernel and the
+CPU oracle's throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 2048
+P = 64
+LEVELS = 5
+TAU = 0.6
+SEED = 0
+PRIMARY_EPS = 1e-4
+TARGET_REL_L2 = 1e-3
+
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed-FP32 instructions: 256 CUs x 64 lanes x
+# 2 flops (FMA) x 2.4 GHz.
+VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def line_flops(s: int, levels: int) -> int:
+    """FP32 flops of one multi-level folded BL5/3 pass over a line of s = 2^J + 1 nodes.
+
+    Per level with m details: predict = add + fused multiply-add (3 flops) per
+    detail, update = two fused multiply-adds (4 flops) per interior sample.
+    """
+    tot = 0
+    for lev in range(1, levels + 1):
+        m = (s - 1) >> lev
+        tot += 3 * m + 4 * (m - 1)
+    return tot
+
+
+def flops_per_patch(p: int = P, levels: int = LEVELS, nfields: int = 9) -> int:
+    """Algorithmic FP32 flops of one patch step: three 2-D transforms (inverse,
+    forward, re-inverse) of every field plus the D2Q9 collision of every node
+    (126 flops: 18 for the moments, 9 for the velocity, 99 for the nine
+    equilibria and relaxations)."""
+    s = p + 1
+    transforms = 3 * nfields * 2 * s * line_flops(s, levels)
+    return transforms + 126 * s * s
+
+
+def halo_bytes(npatch: int) -> int:
+    """Halo strips written (and read) per step: 4 sides x 3 populations x 65 nodes x 4 B per patch."""
+    return npatch * 4 * 3 * (P + 1) * 4
+
+
+def run_point(eps: float, steps: int, warmup: int, macro, ref_state):
+    import torch
+
+    from paper_2302_09883_amd import Context
+
+    ctx = Context(N, scheme="d2q9_bgk", dtype="f32", p=P, wavelet="bl53", levels=LEVELS, eps=eps, tau=TAU)
+    ctx.set_macroscopic(*macro)
+    ctx.step(warmup)
+    s0 = ctx.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = ctx.stats()
+    wall = t1 - t0
+    ev_ms = s1["ms_last_call"]
+    state = ctx.fields()
+    d = state.astype(np.float64) - ref_state
+    rel = float(np.linalg.norm(d) / np.linalg.norm(ref_state))
+    linf = float(np.max(np.abs(d)))
+    paper_l2 = float((1.0 / N) ** 2 * np.sum(d * d))
+    npatch = (N // P) ** 2
+    store_avg = 0.5 * (s0["store_bytes"] + s1["store_bytes"])
+    bytes_launch = 2.0 * store_avg + 2.0 * halo_bytes(npatch)
+    ncoef = npatch * 9 * (P + 1) ** 2
+    out = {
+        "eps": eps,
+        "mlups": N * N * steps / wall / 1e6,
+        "mlups_events": N * N * steps / (ev_ms * 1e-3) / 1e6,
+        "ms_per_step": wall * 1e3 / steps,
+        "kernel_ms_avg": ev_ms / steps,
+        "ratio": s1["ratio"],
+        "store_bytes": s1["store_bytes"],
+        "rho_nz": s1["nnz_total"] / ncoef,
+        "rel_l2": rel,
+        "linf": linf,
+        "paper_l2": paper_l2,
+        "bytes_per_launch": bytes_launch,
+        "regrows": s1["regrows"],
+        "mass_drift": (s1["totals"][0] + sum(s1["totals"][1:])) / (s0["totals"][0] + sum(s0["totals"][1:])) - 1.0,
+    }
+    ctx.close()
+    return out
+
+
+def reference_state(macro, total_steps: int):
+    import torch
+
+    from paper_2302_09883_amd import Context
+
+    ref = Context(N, scheme="d2q9_bgk", dtype="f32", reference=True, tau=TAU)
+    ref.set_macroscopic(*macro)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref.step(total_steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = ref.fields().astype(np.float64)
+    mlups = N * N * total_steps / (t1 - t0) / 1e6
+    ref.close()
+    return st, mlups
+
+
+def cr_at_error(points, target):
+    """Log-log interpolation of the compression ratio at a relative L2 error."""
+    pts = sorted((p["rel_l2"], p["ratio"], p["eps"]) for p in points if p["rel_l2"] > 0)
+    for (e0, c0, k0), (e1, c1, k1) in zip(pts, pts[1:]):
+        if e0 <= target <= e1 and e1 > e0:
+            w = (math.log(target) - math.log(e0)) / (math.log(e1) - math.log(e0))
+            return {"target_rel_l2": target, "ratio": math.exp(math.log(c0) + w * (math.log(c1) - math.log(c0))),
+                    "bracket_eps": [k0, k1]}
+    return {"target_rel_l2": target, "ratio": None, "bracket_eps": None,
+            "note": "target outside the sweep's error range"}
+
+
+def cpu_baseline(block: int = 8):
+    """The oracle (float32, single-threaded NumPy) on a bounded sample.
+
+    Sample: one step of the patch loop over a ``block`` x ``block`` block of
+    patches of the same workload (state compressed from the same initial
+    condition): inverse transform of the block and its ring of neighbours
+    (the ghost source), ghost gathering, stencil, forward transform,
+    threshold and record encoding of the block.  Throughput in MLUPS over the
+    block's owned cells.
+    """
+    from oracle import lbmz_oracle as O
+    from synth import shear_layer_macroscopic
+
+    rho, ux, uy = shear_layer_macroscopic(N, seed=SEED)
+    grid = O.d2q9_equilibrium(rho, ux, uy).astype(np.float32)
+    g = O.Geometry(N, P, O.BL53, LEVELS)
+    run = O.CompressedRun(g, O.Scheme("d2q9_bgk", tau=TAU), PRIMARY_EPS, O.RULE_CAPPED, np.float32)
+    coef = run.compress_tiles(O.extract_tiles(grid, g))
+    npx = g.npx
+    blk = [px + npx * py for py in range(block) for px in range(block)]
+    ring = sorted({(px % npx) + npx * (py % npx) for py in range(-1, block + 1) for px in range(-1, block + 1)})
+    t0 = time.perf_counter()
+    lossy = np.zeros_like(coef)
+    lossy[ring] = run.decompress_tiles(coef[ring])
+    padded = O.gather_ghosts(lossy, g)[blk]
+    new = run.compress_tiles(run.scheme.update(padded).astype(np.float32))
+    for q in range(len(blk)):
+        for f in range(9):
+            O.encode_record(np.ascontiguousarray(new[q, f]).reshape(-1))
+    dt = time.perf_counter() - t0
+    return {"value": len(blk) * P * P / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"one step of a {block}x{block} block of the 32x32 patches (64x64 cells each) of the "
+                      f"2048^2 D2Q9 workload at eps={PRIMARY_EPS}, float32 NumPy oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--eps", type=float, nargs="*", default=[1e-5, 1e-4, 1e-3])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-block", type=int, default=32)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the compressed patch loop runs on a single MI355X "
+              "(multi-GPU sharding is a design note only); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from synth import shear_layer_macroscopic
+
+    torch.cuda.set_device(0)
+    rho, ux, uy = shear_layer_macroscopic(N, seed=SEED)
+    macro = tuple(a.astype(np.float32) for a in (rho, ux, uy))
+    ref_state, ref_mlups = reference_state(macro, args.warmup + args.steps)
+
+    eps_list = list(dict.fromkeys(args.eps + [PRIMARY_EPS]))
+    points = [run_point(e, args.steps, args.warmup, macro, ref_state) for e in sorted(eps_list)]
+    prim = next(p for p in points if p["eps"] == PRIMARY_EPS)
+
+    npatch = (N // P) ** 2
+    ksec = prim["kernel_ms_avg"] * 1e-3
+    hbm_gbs = prim["bytes_per_launch"] / ksec / 1e9
+    flops_launch = flops_per_patch() * npatch
+    tflops = flops_launch / ksec / 1e12
+    hbm_frac = hbm_gbs / HBM_PEAK_GBS
+    alu_frac = tflops / VALU_PEAK_TFLOPS
+    if alu_frac >= hbm_frac:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": None,
+                "hbm": {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(hbm_frac, 4)}}
+    else:
+        roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4), "traffic": None,
+                "alu": {"achieved": round(tflops, 3), "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                        "frac": round(alu_frac, 4)}}
+    roof["kernel"] = "patch_step_kernel<float, 64, BL53, D2Q9>"
+    roof["flops_per_launch"] = flops_launch
+    roof["bytes_per_launch"] = round(prim["bytes_per_launch"])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_block)
+
+    line = {
+        "metric": "MLUPS incl. compress/decompress + compression ratio at fixed L2 error",
+        "value": round(prim["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(prim["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D2Q9 BGK tau=0.6, 2048x2048 periodic, 64x64 patches, folded BL5/3 L=5, "
+                               "capped threshold, double shear layer",
+                   "grid": N, "patch": P, "levels": LEVELS, "eps": PRIMARY_EPS, "parallelism": "single GPU"},
+        "compression_ratio": round(prim["ratio"], 2),
+        "rel_l2_vs_uncompressed": prim["rel_l2"],
+        "cr_at_fixed_l2": cr_at_error(points, TARGET_REL_L2),
+        "sweep": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in p.items()} for p in points],
+        "uncompressed_mlups": round(ref_mlups, 1),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -58,3 +58,9 @@ bool dispatch_f32_lbm(const KernelKey& k, int op, const PatchArgs* a, int npatch
 }
 
 }  // namespace lbmz
+
+#ifdef LBMZ_PHASE_CLOCK
+extern "C" int lbmz_debug_phase_clock(void* dst, size_t bytes) {
+  return (int)hipMemcpyFromSymbol(dst, HIP_SYMBOL(lbmz::lbmz_phase_clock), bytes, 0, hipMemcpyDeviceToHost);
+}
+#endif

@@ -704,6 +704,20 @@ __device__ __forceinline__ void field_totals(double* out, const T* tile, double*
 // Kernels
 // ---------------------------------------------------------------------------
 
+// Optional per-phase wall-clock marks of the step kernel (profiling builds
+// compiled with -DLBMZ_PHASE_CLOCK; the product build has none).
+#ifdef LBMZ_PHASE_CLOCK
+static __device__ unsigned long long lbmz_phase_clock[4096 * 16];
+#define LBMZ_MARK(k)                                                                  \
+  do {                                                                                \
+    if (threadIdx.x == 0 && blockIdx.x < 4096) lbmz_phase_clock[blockIdx.x * 16 + (k)] = wall_clock64(); \
+  } while (0)
+#else
+#define LBMZ_MARK(k) \
+  do {               \
+  } while (0)
+#endif
+
 #define LBMZ_PATCH_SHARED(C, T)                                   \
   __shared__ T s_tile[C::M * C::FS];                              \
   __shared__ T s_ghost[4 * C::NSLOT * C::GL];                     \
@@ -729,17 +743,25 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(P
   }
   __syncthreads();
   if (s_misc[2] != 0u) return;
+  LBMZ_MARK(0);
   gather_ghosts<C, T, SCH>(a, q, s_ghost);
   expand<C, T>(a.pool_in, a.table_in, q, s_tile, s_fi, s_w, s_words);
+  LBMZ_MARK(1);
   inverse_transform<C, T, WAV>(s_tile, a.levels);
+  LBMZ_MARK(2);
   if constexpr (SCH == S_LBM) stencil_lbm<C, T>(a, s_tile, s_ghost);
   else stencil_fv<C, T>(a, s_tile, s_ghost);
+  LBMZ_MARK(3);
   forward_transform_threshold<C, T, WAV>(s_tile, a.levels, T(a.eps), a.rule);
+  LBMZ_MARK(4);
   if (!compact<C, T>(a, q, s_tile, s_fi, s_w, s_misc)) return;
   __syncthreads();
+  LBMZ_MARK(5);
   inverse_transform<C, T, WAV>(s_tile, a.levels);
+  LBMZ_MARK(6);
   export_halo<C, T, SCH>(a, q, s_tile);
   field_totals<C, T, WAV>(a.partials_out + (size_t)q * C::M, s_tile, s_red);
+  LBMZ_MARK(7);
 }
 
 // Auxiliary modes (state set-up, store restore, decompression).
