@@ -341,12 +341,19 @@ def hard_threshold(coef: np.ndarray, thr: np.ndarray) -> np.ndarray:
 # Compaction: per-(patch, field) records (the role of CSR, Section 2.3.1)
 # ---------------------------------------------------------------------------
 #
-# Record of one (patch, field) tile with s*s coefficients, index t = x + s*y:
-#   mask[t] = coefficient != 0 (negative zero counts as zero, NaN is kept);
-#   values  = the kept coefficients in ascending t;
-#   then, if 2*nnz < 8*W with W = ceil(s*s / 64): the u16 indices t (an index
-#   list), otherwise W little-endian u64 words with bit (t % 64) of word
-#   (t // 64) set for a kept coefficient (a bitmask);
+# Record order of the coefficients of one (patch, field) tile: the owned
+# p x p block first, row by row (x fastest), then, for bl53 tiles (size
+# p + 1), the shared bordering column x = p (y = 0 .. p-1), the shared row
+# y = p (x = 0 .. p-1) and the shared corner (p, p).  For a Haar tile (size p)
+# this is plain row-major order.  A coefficient's record index k is its
+# position in this order.
+#
+# Record of one tile:
+#   kept[k] = coefficient != 0 (negative zero counts as zero, NaN is kept);
+#   values  = the kept coefficients in ascending k;
+#   then, if 2*nnz < 8*W with W = ceil(s*s / 64): the u16 indices k (an index
+#   list), otherwise W little-endian u64 words with bit (k % 64) of word
+#   (k // 64) set for a kept coefficient (a bitmask);
 #   layout: values, zero padding to a multiple of 8 bytes, the index list or
 #   the mask words, zero padding to a multiple of 16 bytes.
 # Offset table entry per (patch, field): u32 record offset in 16-byte units,
@@ -355,6 +362,21 @@ def hard_threshold(coef: np.ndarray, thr: np.ndarray) -> np.ndarray:
 #   exclusive prefix sum of the previous record sizes.
 
 MASK_BIT = 1 << 31
+
+
+def record_order(s: int) -> np.ndarray:
+    """Flat tile indices (``y * s + x``) in record order for an ``s x s`` tile.
+
+    ``s`` odd means a bl53 tile of ``p = s - 1`` owned cells plus the shared
+    border; ``s`` even means a Haar tile of ``p = s`` cells.
+    """
+    p = s - 1 if s % 2 == 1 else s
+    order = [y * s + x for y in range(p) for x in range(p)]
+    if p != s:
+        order += [y * s + p for y in range(p)]
+        order += [p * s + x for x in range(p)]
+        order += [p * s + p]
+    return np.array(order, dtype=np.int64)
 
 
 def _align(x: int, a: int) -> int:
@@ -370,62 +392,63 @@ def record_layout(nnz: int, ncoef: int, esize: int):
     return is_mask, vb, mb, _align(vb + mb, 16)
 
 
-def encode_record(coef_flat: np.ndarray) -> bytes:
-    """Bytes of one record from a thresholded flat tile (see layout above)."""
-    ncoef = coef_flat.size
-    keep = coef_flat != 0
+def encode_record(tile: np.ndarray) -> bytes:
+    """Bytes of one record from a thresholded ``s x s`` tile (see layout above)."""
+    s = tile.shape[-1]
+    seq = np.ascontiguousarray(tile).reshape(-1)[record_order(s)]
+    ncoef = seq.size
+    keep = seq != 0
     idx = np.flatnonzero(keep)
     nnz = idx.size
-    esize = coef_flat.dtype.itemsize
+    esize = seq.dtype.itemsize
     is_mask, vb, mb, rb = record_layout(nnz, ncoef, esize)
     buf = bytearray(rb)
-    vals = coef_flat[idx].astype(coef_flat.dtype.newbyteorder("<"))
-    buf[0:nnz * esize] = vals.tobytes()
+    buf[0:nnz * esize] = seq[idx].astype(seq.dtype.newbyteorder("<")).tobytes()
     if is_mask:
         w = (ncoef + 63) // 64
         words = np.zeros(w, dtype="<u8")
-        for t in idx:
-            words[t // 64] |= np.uint64(1) << np.uint64(t % 64)
+        for k in idx:
+            words[k // 64] |= np.uint64(1) << np.uint64(k % 64)
         buf[vb:vb + mb] = words.tobytes()
     else:
         buf[vb:vb + mb] = idx.astype("<u2").tobytes()
     return bytes(buf)
 
 
-def decode_record(buf: bytes, off16: int, word: int, ncoef: int, dtype) -> np.ndarray:
-    """Inverse of :func:`encode_record` for the record at ``16 * off16``."""
+def decode_record(buf: bytes, off16: int, word: int, s: int, dtype) -> np.ndarray:
+    """Inverse of :func:`encode_record` for the record at ``16 * off16``; ``s x s`` tile."""
     dtype = np.dtype(dtype)
+    ncoef = s * s
     nnz = word & (MASK_BIT - 1)
     is_mask = bool(word & MASK_BIT)
     base = 16 * off16
-    esize = dtype.itemsize
-    vb = _align(nnz * esize, 8)
+    vb = _align(nnz * dtype.itemsize, 8)
     vals = np.frombuffer(buf, dtype=dtype.newbyteorder("<"), count=nnz, offset=base)
-    out = np.zeros(ncoef, dtype=dtype)
     if is_mask:
         w = (ncoef + 63) // 64
         words = np.frombuffer(buf, dtype="<u8", count=w, offset=base + vb)
-        bits = [(int(words[t // 64]) >> (t % 64)) & 1 for t in range(ncoef)]
+        bits = [(int(words[k // 64]) >> (k % 64)) & 1 for k in range(ncoef)]
         idx = np.flatnonzero(np.array(bits, dtype=bool))
     else:
         idx = np.frombuffer(buf, dtype="<u2", count=nnz, offset=base + vb).astype(np.int64)
-    out[idx] = vals
-    return out
+    seq = np.zeros(ncoef, dtype=dtype)
+    seq[idx] = vals
+    out = np.zeros(ncoef, dtype=dtype)
+    out[record_order(s)] = seq
+    return out.reshape(s, s)
 
 
 def encode_store(coef: np.ndarray):
     """Offset table ``uint32 [npatch, m, 2]`` and pool bytes from ``[npatch, m, s, s]``."""
-    npatch, m = coef.shape[:2]
-    ncoef = coef.shape[2] * coef.shape[3]
+    npatch, m, s = coef.shape[0], coef.shape[1], coef.shape[2]
     table = np.zeros((npatch, m, 2), dtype=np.uint32)
     parts = []
     off = 0
     for q in range(npatch):
         for f in range(m):
-            rec = encode_record(np.ascontiguousarray(coef[q, f]).reshape(-1))
-            flat = coef[q, f].reshape(-1)
-            nnz = int(np.count_nonzero(flat != 0))
-            is_mask = record_layout(nnz, ncoef, coef.dtype.itemsize)[0]
+            rec = encode_record(coef[q, f])
+            nnz = int(np.count_nonzero(coef[q, f] != 0))
+            is_mask = record_layout(nnz, s * s, coef.dtype.itemsize)[0]
             table[q, f, 0] = off // 16
             table[q, f, 1] = nnz | (MASK_BIT if is_mask else 0)
             parts.append(rec)
@@ -439,8 +462,7 @@ def decode_store(table: np.ndarray, pool: bytes, s: int, dtype) -> np.ndarray:
     out = np.zeros((npatch, m, s, s), dtype=dtype)
     for q in range(npatch):
         for f in range(m):
-            out[q, f] = decode_record(pool, int(table[q, f, 0]), int(table[q, f, 1]),
-                                      s * s, dtype).reshape(s, s)
+            out[q, f] = decode_record(pool, int(table[q, f, 0]), int(table[q, f, 1]), s, dtype)
     return out
 
 

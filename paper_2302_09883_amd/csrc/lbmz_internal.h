@@ -33,6 +33,8 @@ constexpr uint32_t MASK_BIT = 0x80000000u;
 struct PatchArgs {
   int n;             // grid cells per side
   int npx;           // patches per side
+  int npatch;        // patches in the grid
+  int grid;          // workgroups resident at once (prefetch distance); 0 = no prefetch
   int levels;        // wavelet levels per dimension
   int rule;          // Rule
   double eps;        // threshold constant

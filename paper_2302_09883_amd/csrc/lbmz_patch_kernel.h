@@ -1,27 +1,27 @@
 // Fused patch kernels for gfx950: one workgroup owns one patch for the whole
 // step and keeps all of its fields in LDS.
 //
-//   S3  ghost ring: strips the neighbours exported at the end of the previous
-//       step (their lossy reconstructions), loaded first so that the loads
-//       overlap the decompression;
-//   S1  expand the patch's records (values + u16 index list or u64 bitmask)
-//       into the LDS tile;
-//   S2  inverse wavelet transform: columns (y), then rows (x), coarse to fine;
-//   S4  stencil update of every tile node (FV upwind flux sum or D2Q9 pull
-//       stream + BGK collision), in place through registers;
-//   S5  forward transform: rows, then columns (the tensor 2-D decomposition of
-//       Section 2.1), with S6, the hard threshold of Section 2.2, applied in
-//       registers at the end of the column pass;
-//   S7  compaction: wave64 ballot of the non-zero mask, per-field prefix sums
-//       of the word counts, one bump allocation per patch in the output pool,
-//       coalesced stores of values and indices or mask words;
-//   S8  inverse transform of the thresholded tile (what neighbours and the
-//       next step will see) and export of the boundary lines they need;
-//   S9  FP64 per-field trapezoid sums of that reconstruction.
+// Lines of a tile are lifted one per thread in registers.  In every pass,
+// wave f (< M) owns field f, lane l its line l (l < P); with the folded
+// BL5/3 tiles (shared bordering line P) wave M owns line P of every field,
+// lane f for field f.  LDS rows use an odd stride so that row-per-lane and
+// column-per-lane accesses are both bank-conflict free.
 //
-// Lifting runs one line per thread entirely in registers (the line is read
-// from LDS once and written back once per pass); LDS rows use an odd stride so
-// that both row-per-lane and column-per-lane access are bank-conflict free.
+// One step of one patch:
+//   S3  ghost values of the neighbours' previous export are loaded first;
+//   S1  the patch's records are expanded straight into the column registers
+//       (bitmask records) or scattered through LDS (index-list records),
+//   S2  inverse transform: columns (y) then rows (x), coarse to fine; for
+//       D2Q9 the row pass also applies the x part of pull streaming;
+//   S4  stencil (D2Q9: y part of streaming by row offsets + BGK collision;
+//       FV: upwind flux sum) of every tile node;
+//   S5  forward transform: rows (x), then in one column pass: columns (y),
+//   S6  hard threshold (Section 2.2),
+//   S7  compaction straight from registers: one ballot per 64-bit mask
+//       word, one bump allocation per patch, coalesced value stores,
+//   S9  FP64 totals from the coarse samples,
+//   S8  column inverse in the same registers, row inverse, and export of
+//       the boundary lines the neighbours need at the next step.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,36 +33,79 @@ namespace lbmz {
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
-template <class T, int P, int WAV, int SCH>
-struct Cfg {
-  static constexpr int S = (WAV == W_BL53) ? P + 1 : P;     // tile nodes per side
-  static constexpr int RS = (S & 1) ? S : S + 1;            // LDS row stride (odd)
-  static constexpr int M = (SCH == S_LBM) ? 9 : 1;          // fields
-  static constexpr int FS = S * RS;                         // LDS field stride
-  static constexpr int NC = S * S;                          // coefficients per field
-  static constexpr int W = (NC + 63) / 64;                  // mask words per field
-  static constexpr int NSLOT = (SCH == S_LBM) ? 3 : M;      // fields crossing one side
-  static constexpr int GL = S + 2;                          // ghost strip length, j = -1 .. S
-  static constexpr int LO = (WAV == W_BL53) ? 1 : 0;        // first line a neighbour needs
-  static constexpr int HI = P - 1;                          // last line a neighbour needs
-  static constexpr int NT = (M * S >= 256) ? 1024 : 256;    // threads per workgroup
-  static constexpr int NWAVES = NT / 64;
-  static constexpr int J = ilog2c(P);
-  static constexpr int LMAX = (WAV == W_BL53) ? J - 1 : J;
-  static constexpr int NPER = (NC + NT - 1) / NT;           // stencil nodes per thread
-  static constexpr int IPW = (M * W + NWAVES - 1) / NWAVES; // mask words per wave
-  static constexpr int LPT = (4 * W + NT - 1) / NT;         // index-list entries per thread
-  static_assert(W <= 128, "tile too large for the two-word-per-lane scans");
-  static_assert(NC <= 65536, "u16 indices");
+struct D2Q9 {
+  static constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  // populations entering through each ghost side: W (x = -1), E (x = S),
+  // S (y = -1), N (y = S), in numbering order (the slot of a population)
+  static constexpr int SIDE_POP[4][3] = {{1, 5, 8}, {3, 6, 7}, {2, 5, 6}, {4, 7, 8}};
 };
 
-struct FieldInfo {
-  uint32_t off16;   // record offset (16-byte units)
-  uint32_t nnz;
-  uint32_t ismask;
-  uint32_t vb;      // bytes of values incl. padding to 8
-  uint32_t rel16;   // record offset inside the patch's allocation
-  uint32_t rb;      // record bytes
+// LDS layout of the fields of a tile.  D2Q9 populations that pull from row
+// y - 1 (c_y = +1) carry one ghost row before row 0, those that pull from
+// row y + 1 carry one after row S - 1; the ghost rows are filled by the halo
+// gather so that streaming in y becomes a fixed row offset.
+template <int SCH, int S, int RS>
+struct TileLayout {
+  static constexpr int M = (SCH == S_LBM) ? 9 : 1;
+  static constexpr int lo(int f) { return (SCH == S_LBM && D2Q9::CY[f] == 1) ? 1 : 0; }
+  static constexpr int hi(int f) { return (SCH == S_LBM && D2Q9::CY[f] == -1) ? 1 : 0; }
+  static constexpr int start(int f) {
+    int s = 0;
+    for (int g = 0; g < f; ++g) s += (S + lo(g) + hi(g)) * RS;
+    return s;
+  }
+  static constexpr int fb(int f) { return start(f) + lo(f) * RS; }   // row 0 of field f
+  static constexpr int total() { return start(M); }
+};
+
+template <class T, int P_, int WAV, int SCH>
+struct Cfg {
+  static constexpr int P = P_;
+  static constexpr bool RIM = (WAV == W_BL53);              // tiles carry the shared line P
+  static constexpr int S = RIM ? P + 1 : P;                 // tile nodes per side
+  static constexpr int RS = (S & 1) ? S : S + 1;            // LDS row stride (odd)
+  static constexpr int M = (SCH == S_LBM) ? 9 : 1;          // fields
+  static constexpr int NC = S * S;                          // coefficients per field
+  static constexpr int W = (NC + 63) / 64;                  // mask words per record
+  static constexpr int CW = P * P / 64;                     // mask words of the owned block
+  static constexpr int RPW = 64 / P;                        // owned rows per mask word
+  static constexpr int NSLOT = (SCH == S_LBM) ? 3 : M;      // fields crossing one side
+  static constexpr int LO = RIM ? 1 : 0;                    // first line a neighbour needs
+  static constexpr int HI = P - 1;                          // last line a neighbour needs
+  static constexpr int NT = (SCH == S_LBM) ? 1024 : 256;    // threads per workgroup
+  static constexpr int NWAVES = NT / 64;
+  static constexpr int J = ilog2c(P);
+  static constexpr int LMAX = RIM ? J - 1 : J;
+  static constexpr int NPER = (NC + NT - 1) / NT;           // stencil nodes per thread
+  static constexpr int NPASS = M + (RIM ? 1 : 0);          // waves with a line in the passes
+  static constexpr int NHT = NT - 64 * NPASS;               // helper threads (no line)
+  static constexpr int LPT = (4 * W + NHT - 1) / NHT;       // index-list entries per helper
+  using Lay = TileLayout<SCH, S, RS>;
+  static constexpr int TILE = Lay::total();
+  static_assert(P >= 8 && P <= 64, "patch size");
+  static_assert(W <= 128, "two mask words per lane");
+  static_assert(NWAVES > NPASS, "one wave per field, one for the shared line, and helpers");
+};
+
+// Shared memory of the patch kernels.
+template <class C, class T>
+struct Smem {
+  T tile[C::TILE];
+  T ghost[4 * C::NSLOT * C::S];          // D2Q9: W/E strips (x shift); FV: W/E/S/N strips
+  unsigned long long rowbits[C::M];      // bits of the shared row y = P (x < P)
+  unsigned long long colbits[C::M];      // bits of the shared column x = P (y < P)
+  double tot[C::M];
+  double totface[C::M];
+  unsigned corner[C::M];
+  unsigned core_nnz[C::M];
+  uint32_t rel16[C::M];                  // record offset inside the patch's allocation
+  uint32_t nnz[C::M];
+  uint32_t ismask[C::M];
+  uint32_t vb[C::M];
+  uint32_t rb[C::M];
+  uint32_t pf_te[2 * C::M];              // offset-table entries of the next patch (prefetch)
+  unsigned misc[4];
 };
 
 // ---------------------------------------------------------------------------
@@ -70,9 +113,16 @@ struct FieldInfo {
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
-__device__ __forceinline__ unsigned mbcnt64(unsigned long long m) {
-  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long below(int b) {   // bits [0, b), 0 <= b <= 63
+  return (1ull << b) - 1ull;
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
@@ -92,14 +142,28 @@ template <> __device__ __forceinline__ double max_finite<double>() { return 1.79
 __device__ __forceinline__ float ldexp_t(float v, int e) { return ldexpf(v, e); }
 __device__ __forceinline__ double ldexp_t(double v, int e) { return ldexp(v, e); }
 
+// Zero n elements from p, threads `t` of `nt` cooperating: 16-byte stores
+// on the aligned body, element stores on the unaligned head and tail.
+template <class T>
+__device__ __forceinline__ void zero_span(T* p, int n, int t, int nt) {
+  constexpr int E = 16 / sizeof(T);
+  const int head = (int)(((16u - ((uintptr_t)p & 15u)) & 15u) / sizeof(T));
+  const int h = head < n ? head : n;
+  const int nv = (n - h) / E;
+  if (t < h) p[t] = T(0);
+  uint4* body = reinterpret_cast<uint4*>(p + h);
+  for (int i = t; i < nv; i += nt) body[i] = make_uint4(0u, 0u, 0u, 0u);
+  const int tail0 = h + nv * E;
+  if (tail0 + t < n) p[tail0 + t] = T(0);
+}
+
+// Row 0 of field f in the tile (f may differ between lanes).
 template <class C>
-__device__ __forceinline__ int lds_index(int t) {
-  if constexpr (C::RS == C::S) {
-    return t;
-  } else {
-    const int y = t / C::S;
-    return y * C::RS + (t - y * C::S);
-  }
+__device__ __forceinline__ int field_base(int f) {
+  int r = 0;
+#pragma unroll
+  for (int g = 0; g < C::M; ++g) r = (f == g) ? C::Lay::fb(g) : r;
+  return r;
 }
 
 // Per-dimension rank of tile index i for an L-level transform: -1 for a sample
@@ -107,6 +171,19 @@ __device__ __forceinline__ int lds_index(int t) {
 __device__ __forceinline__ int dim_rank(int i, int L) {
   if ((i & ((1 << L) - 1)) == 0) return -1;
   return L - 1 - __builtin_ctz((unsigned)i);
+}
+
+// Level class of tile index i: 1 + ctz(i) (the detail level it would have),
+// capped at LMAX + 1, which also stands for index 0 (a sample at any L).
+template <int LMAX>
+__device__ __forceinline__ constexpr int level_class(int i) {
+  if (i == 0) return LMAX + 1;
+  int lev = 1;
+  while ((i & 1) == 0 && lev <= LMAX) {
+    i >>= 1;
+    ++lev;
+  }
+  return lev;
 }
 
 // Threshold of Section 2.2 for a coefficient with ranks (rx, ry); 0 for a
@@ -118,6 +195,57 @@ __device__ __forceinline__ T thr_of(int rx, int ry, T eps, int rule) {
   const int ay = ry < 0 ? 0 : ry;
   const int r = (rule == R_CAPPED) ? (ax > ay ? ax : ay) : (rule == R_ACCUM) ? ax + ay : 0;
   return ldexp_t(eps, r);
+}
+
+// Tile node (x, y) of record index k: the owned P x P block row by row, then
+// (shared border) the column x = P, the row y = P and the corner.
+template <class C>
+__device__ __forceinline__ void record_node(int k, int& x, int& y) {
+  constexpr int PP = C::P * C::P;
+  if (k < PP) { y = k / C::P; x = k - y * C::P; }
+  else if (k < PP + C::P) { x = C::P; y = k - PP; }
+  else if (k < PP + 2 * C::P) { y = C::P; x = k - PP - C::P; }
+  else { x = C::P; y = C::P; }
+}
+
+// Shared-border bits of a bitmask record, after the CW words of the owned
+// block: one bit stream with the column x = P at bits [0, P), the row y = P
+// at bits [P, 2P) and the corner at bit 2P, cut into up to three words.
+template <class C>
+__device__ __forceinline__ void rim_join(unsigned long long col, unsigned long long row, bool corner,
+                                         unsigned long long& r0, unsigned long long& r1, unsigned long long& r2) {
+  const unsigned long long c = corner ? 1ull : 0ull;
+  if constexpr (C::P == 64) {
+    r0 = col;
+    r1 = row;
+    r2 = c;
+  } else if constexpr (C::P == 32) {
+    r0 = col | (row << 32);
+    r1 = c;
+    r2 = 0ull;
+  } else {
+    r0 = col | (row << C::P) | (c << (2 * C::P));
+    r1 = 0ull;
+    r2 = 0ull;
+  }
+}
+
+template <class C>
+__device__ __forceinline__ void rim_split(unsigned long long r0, unsigned long long r1, unsigned long long r2,
+                                          unsigned long long& col, unsigned long long& row, bool& corner) {
+  if constexpr (C::P == 64) {
+    col = r0;
+    row = r1;
+    corner = (r2 & 1ull) != 0ull;
+  } else if constexpr (C::P == 32) {
+    col = r0 & below(32);
+    row = r0 >> 32;
+    corner = (r1 & 1ull) != 0ull;
+  } else {
+    col = r0 & below(C::P);
+    row = (r0 >> C::P) & below(C::P);
+    corner = ((r0 >> (2 * C::P)) & 1ull) != 0ull;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -205,141 +333,248 @@ struct Lift {
   }
 };
 
-// One pass over all lines of all fields.  ROWS: lines along x (row-major in
-// LDS); otherwise along y.  THR: apply the hard threshold after a forward
-// column pass (the column index is then the x index of every element).
-template <class C, class T, int WAV, bool ROWS, bool FWD, bool THR>
-__device__ __forceinline__ void lift_pass(T* tile, int L, T eps, int rule) {
-  using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
-  for (int line = threadIdx.x; line < C::M * C::S; line += C::NT) {
-    const int f = line / C::S;
-    const int r = line - f * C::S;
-    T* base = tile + f * C::FS + (ROWS ? r * C::RS : r);
-    constexpr int STR = ROWS ? 1 : C::RS;
-    T v[C::S];
-#pragma unroll
-    for (int i = 0; i < C::S; ++i) v[i] = base[i * STR];
-    if constexpr (FWD) LF::fwd(v, L); else LF::inv(v, L);
-    if constexpr (THR) {
-      const int rx = dim_rank(r, L);
-#pragma unroll
-      for (int i = 0; i < C::S; ++i) {
-        const T thr = thr_of<T>(rx, dim_rank(i, L), eps, rule);
-        v[i] = (fabs(v[i]) < thr) ? T(0) : v[i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < C::S; ++i) base[i * STR] = v[i];
+// Line of the calling thread in a pass: field f and line index r (a column x
+// in column passes, a row y in row passes).
+template <class C>
+__device__ __forceinline__ bool pass_line(int& f, int& r) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave < C::M) {
+    f = wave;
+    r = lane;
+    return lane < C::P;
   }
+  if (C::RIM && wave == C::M) {
+    f = lane < C::M ? lane : 0;
+    r = C::P;
+    return lane < C::M;
+  }
+  f = 0;
+  r = 0;
+  return false;
 }
 
-template <class C, class T, int WAV>
-__device__ __forceinline__ void inverse_transform(T* tile, int L) {
-  lift_pass<C, T, WAV, false, false, false>(tile, L, T(0), 0);
-  __syncthreads();
-  lift_pass<C, T, WAV, true, false, false>(tile, L, T(0), 0);
-  __syncthreads();
-}
-
-template <class C, class T, int WAV>
-__device__ __forceinline__ void forward_transform_threshold(T* tile, int L, T eps, int rule) {
-  lift_pass<C, T, WAV, true, true, false>(tile, L, eps, rule);
-  __syncthreads();
-  lift_pass<C, T, WAV, false, true, true>(tile, L, eps, rule);
-  __syncthreads();
-}
-
-// Threshold of given coefficients (no transform), same decision as above.
 template <class C, class T>
-__device__ __forceinline__ void threshold_pass(T* tile, int L, T eps, int rule) {
-  for (int f = 0; f < C::M; ++f) {
-    for (int t = threadIdx.x; t < C::NC; t += C::NT) {
-      const int y = t / C::S;
-      const int x = t - y * C::S;
-      const T thr = thr_of<T>(dim_rank(x, L), dim_rank(y, L), eps, rule);
-      T& c = tile[f * C::FS + y * C::RS + x];
-      c = (fabs(c) < thr) ? T(0) : c;
+__device__ __forceinline__ void load_col(T* v, const T* tile, int fb, int x) {
+#pragma unroll
+  for (int y = 0; y < C::S; ++y) v[y] = tile[fb + y * C::RS + x];
+}
+template <class C, class T>
+__device__ __forceinline__ void store_col(const T* v, T* tile, int fb, int x) {
+#pragma unroll
+  for (int y = 0; y < C::S; ++y) tile[fb + y * C::RS + x] = v[y];
+}
+template <class C, class T>
+__device__ __forceinline__ void load_row(T* v, const T* tile, int fb, int y) {
+#pragma unroll
+  for (int x = 0; x < C::S; ++x) v[x] = tile[fb + y * C::RS + x];
+}
+template <class C, class T>
+__device__ __forceinline__ void store_row(const T* v, T* tile, int fb, int y) {
+#pragma unroll
+  for (int x = 0; x < C::S; ++x) tile[fb + y * C::RS + x] = v[x];
+}
+
+// Hard threshold of column x (register index = y).  The threshold of element
+// y depends on y only through its level class, so it is computed once per
+// class per column.
+template <class C, class T>
+__device__ __forceinline__ void threshold_column(T* v, int x, int L, T eps, int rule) {
+  const int rx = dim_rank(x, L);
+  T tl[C::LMAX + 2];
+#pragma unroll
+  for (int k = 1; k <= C::LMAX + 1; ++k) tl[k] = thr_of<T>(rx, (k > L) ? -1 : L - k, eps, rule);
+#pragma unroll
+  for (int y = 0; y < C::S; ++y) {
+    const T thr = tl[level_class<C::LMAX>(y)];
+    v[y] = (fabs(v[y]) < thr) ? T(0) : v[y];
+  }
+}
+
+// S9 partial of one column of coefficients: trapezoid weights of the coarse
+// samples (1/2 on the tile ends for BL5/3), FP64, fixed order.  0 for a
+// detail column.
+template <class C, class T>
+__device__ __forceinline__ double column_sample_sum(const T* v, int x, int L) {
+  if ((x & ((1 << L) - 1)) != 0) return 0.0;
+  double acc = 0.0;
+#pragma unroll
+  for (int y = 0; y < C::S; ++y) {
+    if (level_class<C::LMAX>(y) > L) {
+      const double w = (C::RIM && (y == 0 || y == C::S - 1)) ? 0.5 : 1.0;
+      acc += w * (double)v[y];
     }
   }
-  __syncthreads();
+  const double wx = (C::RIM && (x == 0 || x == C::S - 1)) ? 0.5 : 1.0;
+  return wx * acc;
 }
 
-// ---------------------------------------------------------------------------
-// Halo strips
-// ---------------------------------------------------------------------------
-// Ghost sides: 0 = W (x = -1), 1 = E (x = S), 2 = S (y = -1), 3 = N (y = S).
-// halo[q][side][slot][S] holds the line of patch q that fills the ghost strip
-// `side` of the neighbour on the opposite side: side W <- line x = HI of the
-// west neighbour, E <- line x = LO of the east one, S <- line y = HI of the
-// south one, N <- line y = LO of the north one.  For D2Q9 only the three
-// populations streaming into the neighbour are kept (slots in numbering
-// order); for FV every field is kept.
-
-struct D2Q9 {
-  static constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-  static constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-  // populations entering through each ghost side
-  static constexpr int SIDE_POP[4][3] = {{1, 5, 8}, {3, 6, 7}, {2, 5, 6}, {4, 7, 8}};
-};
-
-template <int SCH>
-__device__ __forceinline__ int side_field(int side, int slot) {
-  if constexpr (SCH == S_LBM) {
-    constexpr int tab[12] = {1, 5, 8, 3, 6, 7, 2, 5, 6, 4, 7, 8};
-    return tab[side * 3 + slot];
-  } else {
-    (void)side;
-    return slot;
+// Waves 0..M-1 reduce the column partials of their field into sm.tot[f]; the
+// shared-column wave stores one partial per lane (field) in sm.totface.
+template <class C, class T>
+__device__ __forceinline__ void totals_partial(double part, Smem<C, T>& sm) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  if (wave < C::M) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+    if (lane == 0) sm.tot[wave] = part;
+  } else if (C::RIM && wave == C::M && lane < C::M) {
+    sm.totface[lane] = part;
   }
 }
 
-// Slot of population i in ghost side `side` (compile-time i in the stencil).
-__host__ __device__ constexpr int pop_slot(int side, int i) {
-  return D2Q9::SIDE_POP[side][0] == i ? 0 : D2Q9::SIDE_POP[side][1] == i ? 1
-       : D2Q9::SIDE_POP[side][2] == i ? 2 : 0;
+// Per-field totals of the patch: by the conservation identity of the lifting
+// (equation "conservation", per dimension), the trapezoid mass of the
+// reconstructed tile is 4^L times the coarse trapezoid mass of its samples,
+// whatever the thresholded details are.
+template <class C, class T>
+__device__ __forceinline__ void totals_finish(double* out, int L, Smem<C, T>& sm) {
+  const int tid = threadIdx.x;
+  if (tid < C::M) {
+    const double s = (double)(1 << L) * (double)(1 << L);
+    out[tid] = s * (sm.tot[tid] + (C::RIM ? sm.totface[tid] : 0.0));
+  }
 }
 
-template <class C, class T, int SCH>
-__device__ __forceinline__ void gather_ghosts(const PatchArgs& a, int q, T* ghost) {
+// ---------------------------------------------------------------------------
+// S3: ghost values
+// ---------------------------------------------------------------------------
+// halo[q][side][slot][S] holds the line of patch q that fills ghost side
+// `side` of the neighbour on the opposite side: W <- line x = HI of the west
+// neighbour, E <- line x = LO of the east one, S <- line y = HI of the south
+// one, N <- line y = LO of the north one.  For D2Q9 only the three
+// populations streaming into the neighbour are kept; for FV every field.
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// D2Q9: W/E strips (rows 0..S-1) for the x shift of the row pass, and the
+// S/N ghost rows of the tile, already shifted in x: row -1 of population i
+// holds f_i(x - c_ix, -1), row S holds f_i(x - c_ix, S).
+template <class C, class T>
+__device__ __forceinline__ void gather_lbm(const PatchArgs& a, int q, T* tile, T* ghost) {
   const T* h = static_cast<const T*>(a.halo_in);
   const int px = q % a.npx;
   const int py = q / a.npx;
-  for (int k = threadIdx.x; k < 4 * C::NSLOT * C::GL; k += C::NT) {
-    const int side = k / (C::NSLOT * C::GL);
-    const int rem = k - side * (C::NSLOT * C::GL);
-    const int slot = rem / C::GL;
-    const int j = rem - slot * C::GL - 1;
-    int nx = px, ny = py, src = j;
+  for (int k = threadIdx.x; k < 4 * 3 * C::S; k += C::NT) {
+    const int side = k / (3 * C::S);
+    const int rem = k - side * (3 * C::S);
+    const int slot = rem / C::S;
+    const int j = rem - slot * C::S;
     if (side < 2) {
-      nx = px + (side == 0 ? -1 : 1);
-      if (j < 0) { ny = py - 1; src = C::HI; }
-      else if (j >= C::S) { ny = py + 1; src = C::LO; }
+      const int nb = wrap(px + (side == 0 ? -1 : 1), a.npx) + a.npx * py;
+      ghost[k] = h[((size_t)(nb * 4 + side) * 3 + slot) * C::S + j];
     } else {
-      ny = py + (side == 2 ? -1 : 1);
-      if (j < 0 || j >= C::S) continue;   // corners come from the W / E strips
+      const int pop = D2Q9::SIDE_POP[side][slot];
+      const int xs = j - D2Q9::CX[pop];
+      const int ox = xs < 0 ? -1 : (xs >= C::S ? 1 : 0);
+      const int xl = xs - C::P * ox;
+      const int nb = wrap(px + ox, a.npx) + a.npx * wrap(py + (side == 2 ? -1 : 1), a.npx);
+      const int row = side == 2 ? -1 : C::S;
+      tile[field_base<C>(pop) + row * C::RS + j] = h[((size_t)(nb * 4 + side) * 3 + slot) * C::S + xl];
     }
-    nx = (nx + a.npx) % a.npx;
-    ny = (ny + a.npx) % a.npx;
-    const int nb = nx + a.npx * ny;
-    ghost[k] = h[((size_t)(nb * 4 + side) * C::NSLOT + slot) * C::S + src];
   }
 }
 
-template <class C, class T, int SCH>
-__device__ __forceinline__ void export_halo(const PatchArgs& a, int q, const T* tile) {
-  T* h = static_cast<T*>(a.halo_out);
+// FV: the four ghost strips (no corners: the flux stencil has five points).
+template <class C, class T>
+__device__ __forceinline__ void gather_fv(const PatchArgs& a, int q, T* ghost) {
+  const T* h = static_cast<const T*>(a.halo_in);
+  const int px = q % a.npx;
+  const int py = q / a.npx;
   for (int k = threadIdx.x; k < 4 * C::NSLOT * C::S; k += C::NT) {
     const int side = k / (C::NSLOT * C::S);
     const int rem = k - side * (C::NSLOT * C::S);
     const int slot = rem / C::S;
     const int j = rem - slot * C::S;
-    const int f = side_field<SCH>(side, slot);
-    int x, y;
-    if (side == 0) { x = C::HI; y = j; }
-    else if (side == 1) { x = C::LO; y = j; }
-    else if (side == 2) { x = j; y = C::HI; }
-    else { x = j; y = C::LO; }
-    h[((size_t)(q * 4 + side) * C::NSLOT + slot) * C::S + j] = tile[f * C::FS + y * C::RS + x];
+    int nx = px, ny = py;
+    if (side < 2) nx = wrap(px + (side == 0 ? -1 : 1), a.npx);
+    else ny = wrap(py + (side == 2 ? -1 : 1), a.npx);
+    const int nb = nx + a.npx * ny;
+    ghost[k] = h[((size_t)(nb * 4 + side) * C::NSLOT + slot) * C::S + j];
+  }
+}
+
+// Slot of D2Q9 population f among those entering through side `side`.
+__device__ __forceinline__ int pop_slot(int side, int f) {
+  return D2Q9::SIDE_POP[side][0] == f ? 0 : (D2Q9::SIDE_POP[side][1] == f ? 1 : 2);
+}
+
+__device__ __forceinline__ bool pop_enters(int side, int f) {
+  return D2Q9::SIDE_POP[side][0] == f || D2Q9::SIDE_POP[side][1] == f || D2Q9::SIDE_POP[side][2] == f;
+}
+
+// ---------------------------------------------------------------------------
+// Row passes
+// ---------------------------------------------------------------------------
+
+enum RowMode : int {
+  ROW_FWD = 0,        // forward x levels
+  ROW_INV = 1,        // inverse x levels
+  ROW_INV_SHIFT = 2,  // inverse, then D2Q9 streaming in x (ghosts at the ends)
+  ROW_INV_EXPORT = 3, // inverse, then export of the lines neighbours need
+  ROW_INV_DENSE = 4   // inverse, then owned nodes to the dense output
+};
+
+template <class C, class T, int WAV, int SCH, int MODE>
+__device__ __forceinline__ void row_pass(const PatchArgs& a, int q, T* tile, const T* ghost) {
+  using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
+  int f, y;
+  if (pass_line<C>(f, y)) {
+    const int fb = field_base<C>(f);
+    T v[C::S];
+    load_row<C>(v, tile, fb, y);
+    if constexpr (MODE == ROW_FWD) LF::fwd(v, a.levels); else LF::inv(v, a.levels);
+    if constexpr (MODE == ROW_INV_SHIFT) {
+      // Streaming in x through the store address: node x of the row goes to
+      // x + c_x; the freed end takes the ghost value (c_x = +1: x = 0 from
+      // the W strip; c_x = -1: x = S - 1 from the E strip).
+      const int cx = pop_enters(0, f) ? 1 : (pop_enters(1, f) ? -1 : 0);
+      T* row = tile + fb + y * C::RS + cx;
+#pragma unroll
+      for (int x = 0; x < C::S; ++x) {
+        if ((x > 0 || cx >= 0) && (x < C::S - 1 || cx <= 0)) row[x] = v[x];
+      }
+      if (cx == 1) tile[fb + y * C::RS] = ghost[(0 * 3 + pop_slot(0, f)) * C::S + y];
+      else if (cx == -1) tile[fb + y * C::RS + C::S - 1] = ghost[(1 * 3 + pop_slot(1, f)) * C::S + y];
+    } else if constexpr (MODE == ROW_INV_EXPORT) {
+      T* h = static_cast<T*>(a.halo_out);
+      const size_t hq = (size_t)q * 4;
+      if constexpr (SCH == S_LBM) {
+        if (pop_enters(0, f)) h[((hq + 0) * 3 + pop_slot(0, f)) * C::S + y] = v[C::HI];
+        if (pop_enters(1, f)) h[((hq + 1) * 3 + pop_slot(1, f)) * C::S + y] = v[C::LO];
+        if (y == C::HI && pop_enters(2, f)) {
+#pragma unroll
+          for (int x = 0; x < C::S; ++x) h[((hq + 2) * 3 + pop_slot(2, f)) * C::S + x] = v[x];
+        }
+        if (y == C::LO && pop_enters(3, f)) {
+#pragma unroll
+          for (int x = 0; x < C::S; ++x) h[((hq + 3) * 3 + pop_slot(3, f)) * C::S + x] = v[x];
+        }
+      } else {
+        h[((hq + 0) * C::NSLOT + f) * C::S + y] = v[C::HI];
+        h[((hq + 1) * C::NSLOT + f) * C::S + y] = v[C::LO];
+        if (y == C::HI) {
+#pragma unroll
+          for (int x = 0; x < C::S; ++x) h[((hq + 2) * C::NSLOT + f) * C::S + x] = v[x];
+        }
+        if (y == C::LO) {
+#pragma unroll
+          for (int x = 0; x < C::S; ++x) h[((hq + 3) * C::NSLOT + f) * C::S + x] = v[x];
+        }
+      }
+    } else if constexpr (MODE == ROW_INV_DENSE) {
+      if (y < C::P) {
+        const int px = q % a.npx;
+        const int py = q / a.npx;
+        T* out = static_cast<T*>(a.dense_out) + ((size_t)f * a.n + (size_t)py * C::P + y) * a.n +
+                 (size_t)px * C::P;
+#pragma unroll
+        for (int x = 0; x < C::P; ++x) out[x] = v[x];
+      }
+    } else {
+      store_row<C>(v, tile, fb, y);
+    }
   }
 }
 
@@ -369,19 +604,11 @@ __device__ __forceinline__ void d2q9_collide(const T* f, T omega, T* out) {
   }
 }
 
+// D2Q9: the x part of streaming was applied by the row pass, so population i
+// of node (x, y) is read at row y - c_iy of its field (a ghost row at the
+// tile edge): a fixed offset per population.
 template <class C, class T>
-__device__ __forceinline__ const T* pop_src(const T* tile, const T* ghost, int i, int sx, int sy,
-                                            int ws, int es, int ss, int ns) {
-  if ((unsigned)sx < (unsigned)C::S && (unsigned)sy < (unsigned)C::S)
-    return tile + i * C::FS + sy * C::RS + sx;
-  if (sx < 0) return ghost + (0 * C::NSLOT + ws) * C::GL + sy + 1;
-  if (sx >= C::S) return ghost + (1 * C::NSLOT + es) * C::GL + sy + 1;
-  if (sy < 0) return ghost + (2 * C::NSLOT + ss) * C::GL + sx + 1;
-  return ghost + (3 * C::NSLOT + ns) * C::GL + sx + 1;
-}
-
-template <class C, class T>
-__device__ __forceinline__ void stencil_lbm(const PatchArgs& a, T* tile, const T* ghost) {
+__device__ __forceinline__ void stencil_lbm(const PatchArgs& a, T* tile) {
   const T omega = T(a.omega);
   T res[C::NPER][9];
 #pragma unroll
@@ -389,12 +616,10 @@ __device__ __forceinline__ void stencil_lbm(const PatchArgs& a, T* tile, const T
     const int t = threadIdx.x + k * C::NT;
     if (t < C::NC) {
       const int y = t / C::S;
-      const int x = t - y * C::S;
+      const int base = y * C::RS + (t - y * C::S);
       T fin[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i)
-        fin[i] = *pop_src<C, T>(tile, ghost, i, x - D2Q9::CX[i], y - D2Q9::CY[i],
-                               pop_slot(0, i), pop_slot(1, i), pop_slot(2, i), pop_slot(3, i));
+      for (int i = 0; i < 9; ++i) fin[i] = tile[C::Lay::fb(i) - D2Q9::CY[i] * C::RS + base];
       d2q9_collide<T>(fin, omega, res[k]);
     }
   }
@@ -404,9 +629,9 @@ __device__ __forceinline__ void stencil_lbm(const PatchArgs& a, T* tile, const T
     const int t = threadIdx.x + k * C::NT;
     if (t < C::NC) {
       const int y = t / C::S;
-      const int x = t - y * C::S;
+      const int base = y * C::RS + (t - y * C::S);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) tile[i * C::FS + y * C::RS + x] = res[k][i];
+      for (int i = 0; i < 9; ++i) tile[C::Lay::fb(i) + base] = res[k][i];
     }
   }
   __syncthreads();
@@ -414,7 +639,7 @@ __device__ __forceinline__ void stencil_lbm(const PatchArgs& a, T* tile, const T
 
 // Finite-volume update of equation "vf_scheme" in the order of the transport
 // listing: W' = W, then W' -= dt/h * (W max(a.N^k,0) + W_k min(a.N^k,0)) for
-// N^0..3 = +x, -x, +y, -y.
+// N^0..3 = +x, -x, +y, -y.  Ghost strips: 0 = W, 1 = E, 2 = S, 3 = N.
 template <class C, class T>
 __device__ __forceinline__ void stencil_fv(const PatchArgs& a, T* tile, const T* ghost) {
   const T r = T(a.dt_over_h);
@@ -423,7 +648,8 @@ __device__ __forceinline__ void stencil_fv(const PatchArgs& a, T* tile, const T*
   T res[C::M][C::NPER];
 #pragma unroll
   for (int f = 0; f < C::M; ++f) {
-    const T* tf = tile + f * C::FS;
+    const T* tf = tile + C::Lay::fb(f);
+    const T* g = ghost + f * C::S;
 #pragma unroll
     for (int k = 0; k < C::NPER; ++k) {
       const int t = threadIdx.x + k * C::NT;
@@ -431,10 +657,10 @@ __device__ __forceinline__ void stencil_fv(const PatchArgs& a, T* tile, const T*
         const int y = t / C::S;
         const int x = t - y * C::S;
         const T w = tf[y * C::RS + x];
-        const T we = (x + 1 < C::S) ? tf[y * C::RS + x + 1] : ghost[(1 * C::NSLOT + f) * C::GL + y + 1];
-        const T ww = (x >= 1) ? tf[y * C::RS + x - 1] : ghost[(0 * C::NSLOT + f) * C::GL + y + 1];
-        const T wn = (y + 1 < C::S) ? tf[(y + 1) * C::RS + x] : ghost[(3 * C::NSLOT + f) * C::GL + x + 1];
-        const T wsd = (y >= 1) ? tf[(y - 1) * C::RS + x] : ghost[(2 * C::NSLOT + f) * C::GL + x + 1];
+        const T we = (x + 1 < C::S) ? tf[y * C::RS + x + 1] : g[(1 * C::NSLOT) * C::S + y];
+        const T ww = (x >= 1) ? tf[y * C::RS + x - 1] : g[(0 * C::NSLOT) * C::S + y];
+        const T wn = (y + 1 < C::S) ? tf[(y + 1) * C::RS + x] : g[(3 * C::NSLOT) * C::S + x];
+        const T wsd = (y >= 1) ? tf[(y - 1) * C::RS + x] : g[(2 * C::NSLOT) * C::S + x];
         T o = w;
         o = o - r * (w * cp0 + we * cm0);
         o = o - r * (w * cp1 + ww * cm1);
@@ -452,7 +678,7 @@ __device__ __forceinline__ void stencil_fv(const PatchArgs& a, T* tile, const T*
       const int t = threadIdx.x + k * C::NT;
       if (t < C::NC) {
         const int y = t / C::S;
-        tile[f * C::FS + y * C::RS + (t - y * C::S)] = res[f][k];
+        tile[C::Lay::fb(f) + y * C::RS + (t - y * C::S)] = res[f][k];
       }
     }
   }
@@ -460,256 +686,13 @@ __device__ __forceinline__ void stencil_fv(const PatchArgs& a, T* tile, const T*
 }
 
 // ---------------------------------------------------------------------------
-// S1: expand records into the LDS tile
-// ---------------------------------------------------------------------------
-// Two rounds of global loads: the offset-table entries, then (in parallel)
-// the mask words and the contiguous values.  Values of bitmask records are
-// staged at the front of their field's tile, read back at their ranks into
-// registers, and written to their positions after a barrier.
-
-template <class C, class T>
-__device__ __forceinline__ void expand(const uint8_t* pool, const uint32_t* table, int q, T* tile,
-                                       FieldInfo* fi, uint16_t* wpre, unsigned long long* words) {
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wave = tid >> 6;
-  if (tid < C::M) {
-    const uint32_t off16 = table[2 * (q * C::M + tid)];
-    const uint32_t word = table[2 * (q * C::M + tid) + 1];
-    const uint32_t nnz = word & ~MASK_BIT;
-    fi[tid].off16 = off16;
-    fi[tid].nnz = nnz;
-    fi[tid].ismask = word >> 31;
-    fi[tid].vb = (nnz * (uint32_t)sizeof(T) + 7u) & ~7u;
-  }
-  __syncthreads();
-
-  // Round 2: words (+ prefix scan), staged values, index-list entries.
-  for (int f = wave; f < C::M; f += C::NWAVES) {
-    if (!fi[f].ismask) continue;
-    const unsigned long long* wsrc =
-        reinterpret_cast<const unsigned long long*>(pool + 16ull * fi[f].off16 + fi[f].vb);
-    const unsigned long long w0 = lane < C::W ? wsrc[lane] : 0ull;
-    const unsigned long long w1 = (64 + lane) < C::W ? wsrc[64 + lane] : 0ull;
-    const int c0 = __popcll(w0);
-    const int c1 = __popcll(w1);
-    const int i0 = wave_incl_scan(c0);
-    const int tot0 = __shfl(i0, 63, 64);
-    const int i1 = wave_incl_scan(c1);
-    if (lane < C::W) { wpre[f * C::W + lane] = (uint16_t)(i0 - c0); words[f * C::W + lane] = w0; }
-    if (64 + lane < C::W) {
-      wpre[f * C::W + 64 + lane] = (uint16_t)(tot0 + i1 - c1);
-      words[f * C::W + 64 + lane] = w1;
-    }
-  }
-  T lv[C::M][C::LPT];
-  int li[C::M][C::LPT];
-#pragma unroll
-  for (int f = 0; f < C::M; ++f) {
-    const uint8_t* rec = pool + 16ull * fi[f].off16;
-    const T* vals = reinterpret_cast<const T*>(rec);
-    const uint32_t nnz = fi[f].nnz;
-    if (fi[f].ismask) {
-      for (int k = tid; k < (int)nnz; k += C::NT) tile[f * C::FS + k] = vals[k];
-#pragma unroll
-      for (int u = 0; u < C::LPT; ++u) li[f][u] = -1;
-    } else {
-      const uint16_t* idx = reinterpret_cast<const uint16_t*>(rec + fi[f].vb);
-#pragma unroll
-      for (int u = 0; u < C::LPT; ++u) {
-        const int k = tid + u * C::NT;
-        li[f][u] = -1;
-        if (k < (int)nnz) { li[f][u] = idx[k]; lv[f][u] = vals[k]; }
-      }
-    }
-  }
-  __syncthreads();
-
-  // Round 3 (LDS only): staged values -> registers, then tile positions.
-  T vv[C::IPW];
-#pragma unroll
-  for (int u = 0; u < C::IPW; ++u) {
-    const int item = wave + u * C::NWAVES;
-    vv[u] = T(0);
-    if (item < C::M * C::W) {
-      const int f = item / C::W;
-      if (fi[f].ismask) {
-        const unsigned long long w = words[item];
-        if ((w >> lane) & 1ull) vv[u] = tile[f * C::FS + wpre[item] + mbcnt64(w)];
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < C::IPW; ++u) {
-    const int item = wave + u * C::NWAVES;
-    if (item < C::M * C::W) {
-      const int f = item / C::W;
-      const int t = (item - f * C::W) * 64 + lane;
-      if (fi[f].ismask && t < C::NC) tile[f * C::FS + lds_index<C>(t)] = vv[u];
-    }
-  }
-#pragma unroll
-  for (int f = 0; f < C::M; ++f) {
-    if (!fi[f].ismask) {
-      for (int t = tid; t < C::NC; t += C::NT) tile[f * C::FS + lds_index<C>(t)] = T(0);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int f = 0; f < C::M; ++f) {
-#pragma unroll
-    for (int u = 0; u < C::LPT; ++u) {
-      const int t = li[f][u];
-      if (t >= 0 && t < C::NC) tile[f * C::FS + lds_index<C>(t)] = lv[f][u];
-    }
-  }
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// S7: compaction into the output pool
-// ---------------------------------------------------------------------------
-// Returns false (uniformly) when the pool overflowed; the records are then not
-// written and the host replays the step with a larger pool.
-
-template <class C, class T>
-__device__ __forceinline__ bool compact(const PatchArgs& a, int q, const T* tile, FieldInfo* fi,
-                                        uint16_t* wcnt, unsigned* misc) {
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wave = tid >> 6;
-  bool bad = false;
-  for (int item = wave; item < C::M * C::W; item += C::NWAVES) {
-    const int f = item / C::W;
-    const int t = (item - f * C::W) * 64 + lane;
-    const T v = (t < C::NC) ? tile[f * C::FS + lds_index<C>(t)] : T(0);
-    bad |= !(fabs(v) <= max_finite<T>());
-    const unsigned long long b = __ballot(v != T(0));
-    if (lane == 0) wcnt[item] = (uint16_t)__popcll(b);
-  }
-  if (__ballot(bad) != 0ull && lane == 0) {
-    atomicOr(&a.ctrl->abort, ABORT_NONFINITE);
-    atomicMin(&a.ctrl->abort_epoch, a.epoch);
-  }
-  __syncthreads();
-  for (int f = wave; f < C::M; f += C::NWAVES) {
-    const int c0 = lane < C::W ? (int)wcnt[f * C::W + lane] : 0;
-    const int c1 = (64 + lane) < C::W ? (int)wcnt[f * C::W + 64 + lane] : 0;
-    const int i0 = wave_incl_scan(c0);
-    const int tot0 = __shfl(i0, 63, 64);
-    const int i1 = wave_incl_scan(c1);
-    const int tot1 = __shfl(i1, 63, 64);
-    if (lane < C::W) wcnt[f * C::W + lane] = (uint16_t)(i0 - c0);
-    if (64 + lane < C::W) wcnt[f * C::W + 64 + lane] = (uint16_t)(tot0 + i1 - c1);
-    if (lane == 0) fi[f].nnz = (uint32_t)(tot0 + tot1);
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t acc16 = 0;
-    for (int f = 0; f < C::M; ++f) {
-      const uint32_t nnz = fi[f].nnz;
-      const uint32_t ismask = (2u * nnz < 8u * C::W) ? 0u : 1u;
-      const uint32_t vb = (nnz * (uint32_t)sizeof(T) + 7u) & ~7u;
-      const uint32_t mb = ismask ? 8u * C::W : 2u * nnz;
-      const uint32_t rb16 = (vb + mb + 15u) / 16u;
-      fi[f].ismask = ismask;
-      fi[f].vb = vb;
-      fi[f].rel16 = acc16;
-      fi[f].rb = rb16 * 16u;
-      acc16 += rb16;
-    }
-    const unsigned long long base =
-        atomicAdd(&a.ctrl->top16[a.epoch % 3u], (unsigned long long)acc16);
-    const bool ok = base + acc16 <= a.cap16;
-    if (!ok) {
-      atomicOr(&a.ctrl->abort, ABORT_OVERFLOW);
-      atomicMin(&a.ctrl->abort_epoch, a.epoch);
-    }
-    misc[0] = ok ? 1u : 0u;
-    misc[1] = (unsigned)base;
-  }
-  __syncthreads();
-  if (!misc[0]) return false;
-  const uint32_t base16 = misc[1];
-  if (tid < C::M) {
-    a.table_out[2 * (q * C::M + tid)] = base16 + fi[tid].rel16;
-    a.table_out[2 * (q * C::M + tid) + 1] = fi[tid].nnz | (fi[tid].ismask ? MASK_BIT : 0u);
-  }
-  for (int item = wave; item < C::M * C::W; item += C::NWAVES) {
-    const int f = item / C::W;
-    const int wd = item - f * C::W;
-    const int t = wd * 64 + lane;
-    const T v = (t < C::NC) ? tile[f * C::FS + lds_index<C>(t)] : T(0);
-    const bool keep = v != T(0);
-    const unsigned long long b = __ballot(keep);
-    uint8_t* rec = a.pool_out + 16ull * (base16 + fi[f].rel16);
-    const uint32_t rank = wcnt[item] + mbcnt64(b);
-    if (keep) reinterpret_cast<T*>(rec)[rank] = v;
-    if (fi[f].ismask) {
-      if (lane == 0) reinterpret_cast<unsigned long long*>(rec + fi[f].vb)[wd] = b;
-    } else if (keep) {
-      reinterpret_cast<uint16_t*>(rec + fi[f].vb)[rank] = (uint16_t)t;
-    }
-  }
-  if (tid < C::M) {
-    uint8_t* rec = a.pool_out + 16ull * (base16 + fi[tid].rel16);
-    const uint32_t vend = fi[tid].nnz * (uint32_t)sizeof(T);
-    if (vend < fi[tid].vb) *reinterpret_cast<uint32_t*>(rec + vend) = 0u;
-    const uint32_t mend = fi[tid].vb + (fi[tid].ismask ? 8u * C::W : 2u * fi[tid].nnz);
-    for (uint32_t o = mend; o < fi[tid].rb; o += 2) *reinterpret_cast<uint16_t*>(rec + o) = 0;
-  }
-  return true;
-}
-
-// ---------------------------------------------------------------------------
-// S9: FP64 trapezoid sums per field (fixed reduction order)
-// ---------------------------------------------------------------------------
-
-template <class C, class T, int WAV>
-__device__ __forceinline__ void field_totals(double* out, const T* tile, double* red) {
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wave = tid >> 6;
-  double acc[C::M];
-#pragma unroll
-  for (int f = 0; f < C::M; ++f) acc[f] = 0.0;
-  for (int t = tid; t < C::NC; t += C::NT) {
-    const int y = t / C::S;
-    const int x = t - y * C::S;
-    double w = 1.0;
-    if constexpr (WAV == W_BL53) {
-      if (x == 0 || x == C::S - 1) w *= 0.5;
-      if (y == 0 || y == C::S - 1) w *= 0.5;
-    }
-#pragma unroll
-    for (int f = 0; f < C::M; ++f) acc[f] += w * (double)tile[f * C::FS + y * C::RS + x];
-  }
-#pragma unroll
-  for (int f = 0; f < C::M; ++f) {
-    double v = acc[f];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    if (lane == 0) red[wave * C::M + f] = v;
-  }
-  __syncthreads();
-  if (tid < C::M) {
-    double s = 0.0;
-    for (int w = 0; w < C::NWAVES; ++w) s += red[w * C::M + tid];
-    out[tid] = s;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Kernels
-// ---------------------------------------------------------------------------
-
 // Optional per-phase wall-clock marks of the step kernel (profiling builds
 // compiled with -DLBMZ_PHASE_CLOCK; the product build has none).
+// ---------------------------------------------------------------------------
 #ifdef LBMZ_PHASE_CLOCK
 static __device__ unsigned long long lbmz_phase_clock[4096 * 16];
-#define LBMZ_MARK(k)                                                                  \
-  do {                                                                                \
+#define LBMZ_MARK(k)                                                                                    \
+  do {                                                                                                  \
     if (threadIdx.x == 0 && blockIdx.x < 4096) lbmz_phase_clock[blockIdx.x * 16 + (k)] = wall_clock64(); \
   } while (0)
 #else
@@ -718,61 +701,468 @@ static __device__ unsigned long long lbmz_phase_clock[4096 * 16];
   } while (0)
 #endif
 
-#define LBMZ_PATCH_SHARED(C, T)                                   \
-  __shared__ T s_tile[C::M * C::FS];                              \
-  __shared__ T s_ghost[4 * C::NSLOT * C::GL];                     \
-  __shared__ uint16_t s_w[C::M * C::W];                           \
-  __shared__ unsigned long long s_words[C::M * C::W];             \
-  __shared__ FieldInfo s_fi[C::M];                                \
-  __shared__ double s_red[C::NWAVES * C::M];                      \
-  __shared__ unsigned s_misc[4];
+// ---------------------------------------------------------------------------
+// S1 (+ the column half of S2): records -> inverse-transformed columns in LDS
+// ---------------------------------------------------------------------------
+// Bitmask records are read straight into the column registers: the mask
+// words and their prefix counts come from one load per lane, and the value of
+// column x, row y sits at the prefix of its word plus the set bits below it.
+// Index-list records (sparse) are scattered into a zeroed LDS tile first.
+// With TOT, the S9 totals of the stored coefficients are taken on the way.
 
-// One step (time n -> n + 1) of one patch: S3, S1, S2, S4, S5+S6, S7, S8, S9.
+template <class C, class T, int WAV, bool TOT>
+__device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, Smem<C, T>& sm) {
+  using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const int L = a.levels;
+  const uint32_t* te = a.table_in + 2 * (size_t)q * C::M;
+  const uint8_t* pool = a.pool_in;
+
+  // Index-list records: the helper waves (no line in the passes) load their
+  // entries and zero their tiles, so that the line waves carry no list state.
+  const bool helper = wave >= C::NPASS;
+  const int ht = tid - 64 * C::NPASS;
+  T lv[C::M][C::LPT];
+  int li[C::M][C::LPT];
+  if (helper) {
+#pragma unroll
+    for (int f = 0; f < C::M; ++f) {
+      const uint32_t w = te[2 * f + 1];
+      const uint32_t nnz = w & ~MASK_BIT;
+#pragma unroll
+      for (int u = 0; u < C::LPT; ++u) {
+        li[f][u] = -1;
+        lv[f][u] = T(0);
+      }
+      if (!(w & MASK_BIT)) {
+        const uint8_t* rec = pool + 16ull * te[2 * f];
+        const uint16_t* idx = reinterpret_cast<const uint16_t*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
+#pragma unroll
+        for (int u = 0; u < C::LPT; ++u) {
+          const int k = ht + u * C::NHT;
+          if (k < (int)nnz) {
+            li[f][u] = idx[k];
+            lv[f][u] = reinterpret_cast<const T*>(rec)[k];
+          }
+        }
+        zero_span<T>(sm.tile + C::Lay::fb(f), C::S * C::RS, ht, C::NHT);
+      }
+    }
+  }
+
+  // Bitmask records, owned columns (waves 0..M-1).
+  if (wave < C::M) {
+    const int f = wave;
+    const uint32_t w = te[2 * f + 1];
+    if (w & MASK_BIT) {
+      const uint32_t nnz = w & ~MASK_BIT;
+      const uint8_t* rec = pool + 16ull * te[2 * f];
+      const T* vals = reinterpret_cast<const T*>(rec);
+      const unsigned long long* words =
+          reinterpret_cast<const unsigned long long*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
+      const unsigned long long w0 = lane < C::W ? words[lane] : 0ull;
+      const unsigned long long w1 = (64 + lane) < C::W ? words[64 + lane] : 0ull;
+      const int c0 = __popcll(w0);
+      const int c1 = __popcll(w1);
+      const int i0 = wave_incl_scan(c0);
+      const int tot0 = __shfl(i0, 63, 64);
+      const int i1 = wave_incl_scan(c1);
+      const int p0 = i0 - c0;
+      const int p1 = tot0 + i1 - c1;
+      const int x = lane;
+      const bool act = x < C::P;
+      T v[C::S];
+#pragma unroll
+      for (int y = 0; y < C::S; ++y) {
+        // word and bit of node (x, y): owned rows first, then the shared row
+        const int kw = (y < C::P) ? y / C::RPW : ((C::P == 64) ? C::CW + 1 : C::CW);
+        const int b = (y < C::P) ? x + C::P * (y % C::RPW) : ((C::P == 64) ? x : C::P + x);
+        const unsigned long long wk = kw < 64 ? readlane64(w0, kw) : readlane64(w1, kw - 64);
+        const int pk = kw < 64 ? __builtin_amdgcn_readlane(p0, kw) : __builtin_amdgcn_readlane(p1, kw - 64);
+        v[y] = T(0);
+        if (act && ((wk >> b) & 1ull)) v[y] = vals[pk + __popcll(wk & below(b))];
+      }
+      double part = 0.0;
+      if (act) {
+        if constexpr (TOT) part = column_sample_sum<C, T>(v, x, L);
+        LF::inv(v, L);
+        store_col<C>(v, sm.tile, field_base<C>(f), x);
+      }
+      if constexpr (TOT) totals_partial<C, T>(part, sm);
+    }
+  }
+  // Bitmask records, the shared column x = P (wave M, lane = field).
+  if (C::RIM && wave == C::M && lane < C::M) {
+    const int f = lane;
+    const uint32_t w = te[2 * f + 1];
+    if (w & MASK_BIT) {
+      const uint32_t nnz = w & ~MASK_BIT;
+      const uint8_t* rec = pool + 16ull * te[2 * f];
+      const T* vals = reinterpret_cast<const T*>(rec);
+      const unsigned long long* words =
+          reinterpret_cast<const unsigned long long*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
+      // rim bit stream: column y < P at bit y, row x < P at bit P + x, corner at 2P
+      const unsigned long long r0 = words[C::CW];
+      const unsigned long long r1 = (C::W > C::CW + 1) ? words[C::CW + 1] : 0ull;
+      const unsigned long long r2 = (C::W > C::CW + 2) ? words[C::CW + 2] : 0ull;
+      const int core = (int)nnz - (__popcll(r0) + __popcll(r1) + __popcll(r2));
+      unsigned long long col, rowb;
+      bool corner;
+      rim_split<C>(r0, r1, r2, col, rowb, corner);
+      T v[C::S];
+#pragma unroll
+      for (int y = 0; y < C::P; ++y) {
+        v[y] = T(0);
+        if ((col >> y) & 1ull) v[y] = vals[core + __popcll(col & below(y))];
+      }
+      v[C::P] = corner ? vals[core + __popcll(col) + __popcll(rowb)] : T(0);
+      if constexpr (TOT) sm.totface[f] = column_sample_sum<C, T>(v, C::P, L);
+      LF::inv(v, L);
+      store_col<C>(v, sm.tile, field_base<C>(f), C::P);
+    }
+  }
+  __syncthreads();
+  LBMZ_MARK(12);
+
+  // Index-list records: scatter, then their columns.
+  if (helper) {
+#pragma unroll
+    for (int f = 0; f < C::M; ++f) {
+#pragma unroll
+      for (int u = 0; u < C::LPT; ++u) {
+        const int k = li[f][u];
+        if (k >= 0 && k < C::NC) {
+          int x, y;
+          record_node<C>(k, x, y);
+          sm.tile[C::Lay::fb(f) + y * C::RS + x] = lv[f][u];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  LBMZ_MARK(13);
+  bool any_list = false;
+#pragma unroll
+  for (int g = 0; g < C::M; ++g) any_list |= !(te[2 * g + 1] & MASK_BIT);
+  if (any_list) {
+    int f, x;
+    const bool line = pass_line<C>(f, x);
+    const bool act = line && !(te[2 * f + 1] & MASK_BIT);
+    double part = 0.0;
+    if (act) {
+      T v[C::S];
+      load_col<C>(v, sm.tile, field_base<C>(f), x);
+      if constexpr (TOT) part = column_sample_sum<C, T>(v, x, L);
+      LF::inv(v, L);
+      store_col<C>(v, sm.tile, field_base<C>(f), x);
+    }
+    if constexpr (TOT) {
+      if (wave < C::M) {
+        if (!(te[2 * wave + 1] & MASK_BIT)) totals_partial<C, T>(part, sm);
+      } else if (act) {
+        sm.totface[f] = part;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S5 (column half) + S6 + S7 + S9 + S8 (column half), one column pass
+// ---------------------------------------------------------------------------
+// Returns false (uniformly) when the pool overflowed; the records are then
+// not written and the host replays the step with a larger pool.
+
+template <class C, class T, int WAV, bool FWD>
+__device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C, T>& sm) {
+  using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const int L = a.levels;
+  int f, x;
+  const bool act = pass_line<C>(f, x);
+  T v[C::S];
+#pragma unroll
+  for (int y = 0; y < C::S; ++y) v[y] = T(0);
+  T mag = T(0);
+  double part = 0.0;
+  if (act) {
+    load_col<C>(v, sm.tile, field_base<C>(f), x);
+    if constexpr (FWD) LF::fwd(v, L);
+    threshold_column<C, T>(v, x, L, T(a.eps), a.rule);
+    // Non-finite detection: a scaled sum of magnitudes stays finite for any
+    // finite column and turns into Inf / NaN with any non-finite element.
+#pragma unroll
+    for (int y = 0; y < C::S; ++y) mag = fma(fabs(v[y]), T(0x1p-64), mag);
+    part = column_sample_sum<C, T>(v, x, L);
+  }
+  if (__ballot(!(mag <= max_finite<T>())) != 0ull && lane == 0) {
+    atomicOr(&a.ctrl->abort, ABORT_NONFINITE);
+    atomicMin(&a.ctrl->abort_epoch, a.epoch);
+  }
+  totals_partial<C, T>(part, sm);
+  LBMZ_MARK(8);
+
+  // Counts: one ballot per owned row (and the shared row); the shared column
+  // is held by the lanes of wave M, one field per lane.
+  if (wave < C::M) {
+    int run = 0;
+#pragma unroll
+    for (int y = 0; y < C::P; ++y) run += __popcll(__ballot(act && v[y] != T(0)));
+    unsigned long long rowb = 0ull;
+    if constexpr (C::RIM) rowb = __ballot(act && v[C::P] != T(0));
+    if (lane == 0) {
+      sm.core_nnz[wave] = (unsigned)run;
+      sm.rowbits[wave] = rowb;
+    }
+  } else if (C::RIM && wave == C::M && act) {
+    unsigned long long col = 0ull;
+#pragma unroll
+    for (int y = 0; y < C::P; ++y) col |= (v[y] != T(0) ? 1ull : 0ull) << y;
+    sm.colbits[f] = col;
+    sm.corner[f] = v[C::P] != T(0) ? 1u : 0u;
+  }
+  __syncthreads();
+  LBMZ_MARK(9);
+
+  // Record layouts (lane g of wave 0 for field g), offsets inside the patch
+  // by a wave scan, and one allocation for the patch.
+  if (wave == 0) {
+    uint32_t rb16 = 0;
+    if (lane < C::M) {
+      uint32_t nnz = sm.core_nnz[lane];
+      if constexpr (C::RIM)
+        nnz += (uint32_t)(__popcll(sm.colbits[lane]) + __popcll(sm.rowbits[lane])) + sm.corner[lane];
+      const uint32_t ismask = (2u * nnz < 8u * C::W) ? 0u : 1u;
+      const uint32_t vb = (nnz * (uint32_t)sizeof(T) + 7u) & ~7u;
+      const uint32_t mb = ismask ? 8u * C::W : 2u * nnz;
+      rb16 = (vb + mb + 15u) / 16u;
+      sm.nnz[lane] = nnz;
+      sm.ismask[lane] = ismask;
+      sm.vb[lane] = vb;
+      sm.rb[lane] = rb16 * 16u;
+    }
+    const int incl = wave_incl_scan((int)rb16);
+    const int total = __shfl(incl, 63, 64);
+    if (lane < C::M) sm.rel16[lane] = (uint32_t)(incl - (int)rb16);
+    if (lane == 0) {
+      const unsigned long long base = atomicAdd(&a.ctrl->top16[a.epoch % 3u], (unsigned long long)total);
+      const bool ok = base + (unsigned long long)total <= a.cap16;
+      if (!ok) {
+        atomicOr(&a.ctrl->abort, ABORT_OVERFLOW);
+        atomicMin(&a.ctrl->abort_epoch, a.epoch);
+      }
+      sm.misc[0] = ok ? 1u : 0u;
+      sm.misc[1] = (unsigned)base;
+    }
+  }
+  __syncthreads();
+  LBMZ_MARK(10);
+  if (!sm.misc[0]) return false;
+  const uint32_t base16 = sm.misc[1];
+  if (tid < C::M) {
+    a.table_out[2 * (q * C::M + tid)] = base16 + sm.rel16[tid];
+    a.table_out[2 * (q * C::M + tid) + 1] = sm.nnz[tid] | (sm.ismask[tid] ? MASK_BIT : 0u);
+  }
+
+  // Stores: the rank of a kept coefficient is the count of kept ones in the
+  // rows before it plus the kept lanes below it in its row (mbcnt).
+  if (wave < C::M) {
+    uint8_t* rec = a.pool_out + 16ull * (base16 + sm.rel16[f]);
+    T* vals = reinterpret_cast<T*>(rec);
+    const bool ismask = sm.ismask[f] != 0u;
+    uint16_t* idx = reinterpret_cast<uint16_t*>(rec + sm.vb[f]);
+    unsigned long long myw = 0ull;
+    unsigned long long wd = 0ull;
+    int run = 0;
+#pragma unroll
+    for (int y = 0; y < C::P; ++y) {
+      const unsigned long long b = __ballot(act && v[y] != T(0));
+      if (b != 0ull) {
+        if (act && v[y] != T(0)) {
+          const int rank = run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+          vals[rank] = v[y];
+          if (!ismask) idx[rank] = (uint16_t)(x + C::P * y);
+        }
+        run += __popcll(b);
+      }
+      if (ismask) {
+        // mask word y / RPW collects RPW rows; lane y / RPW keeps it
+        wd |= b << (C::P * (y % C::RPW));
+        if (y % C::RPW == C::RPW - 1) {
+          if (lane == y / C::RPW) myw = wd;
+          wd = 0ull;
+        }
+      }
+    }
+    if constexpr (C::RIM) {
+      const unsigned long long rowb = sm.rowbits[f];
+      if (act && v[C::P] != T(0)) {
+        const int rank = run + __popcll(sm.colbits[f]) + __popcll(rowb & below(x));
+        vals[rank] = v[C::P];
+        if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + C::P + x);
+      }
+    }
+    if (ismask && lane < C::CW) reinterpret_cast<unsigned long long*>(rec + sm.vb[f])[lane] = myw;
+  } else if (C::RIM && wave == C::M && act) {
+    uint8_t* rec = a.pool_out + 16ull * (base16 + sm.rel16[f]);
+    T* vals = reinterpret_cast<T*>(rec);
+    const bool ismask = sm.ismask[f] != 0u;
+    uint16_t* idx = reinterpret_cast<uint16_t*>(rec + sm.vb[f]);
+    const unsigned long long col = sm.colbits[f];
+    int rank = (int)sm.core_nnz[f];
+#pragma unroll
+    for (int y = 0; y < C::P; ++y) {
+      if ((col >> y) & 1ull) {
+        vals[rank] = v[y];
+        if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + y);
+        ++rank;
+      }
+    }
+    if (sm.corner[f]) {
+      rank += __popcll(sm.rowbits[f]);
+      vals[rank] = v[C::P];
+      if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + 2 * C::P);
+    }
+  }
+  if (tid < C::M) {
+    const int g = tid;
+    uint8_t* rec = a.pool_out + 16ull * (base16 + sm.rel16[g]);
+    if constexpr (C::RIM) {
+      if (sm.ismask[g]) {
+        unsigned long long r[3];
+        rim_join<C>(sm.colbits[g], sm.rowbits[g], sm.corner[g] != 0u, r[0], r[1], r[2]);
+        unsigned long long* wds = reinterpret_cast<unsigned long long*>(rec + sm.vb[g]);
+#pragma unroll
+        for (int j = 0; j < C::W - C::CW; ++j) wds[C::CW + j] = r[j];
+      }
+    }
+    const uint32_t vend = sm.nnz[g] * (uint32_t)sizeof(T);
+    if (vend < sm.vb[g]) *reinterpret_cast<uint32_t*>(rec + vend) = 0u;
+    const uint32_t mend = sm.vb[g] + (sm.ismask[g] ? 8u * C::W : 2u * sm.nnz[g]);
+    for (uint32_t o = mend; o < sm.rb[g]; o += 2) *reinterpret_cast<uint16_t*>(rec + o) = 0;
+  }
+  totals_finish<C, T>(a.partials_out + (size_t)q * C::M, L, sm);
+  LBMZ_MARK(11);
+
+  // S8, column half: inverse of the thresholded column, back to LDS.
+  if (act) {
+    LF::inv(v, L);
+    store_col<C>(v, sm.tile, field_base<C>(f), x);
+  }
+  __syncthreads();
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Prefetch of the next patch of a workgroup
+// ---------------------------------------------------------------------------
+// The helper waves (no line in the passes) touch the next patch's offset-table
+// entries, the cache lines of its records and its halo sources while the
+// current patch computes, so that its expansion finds them in L2.  The loaded
+// words are folded into one value that is consumed at the end of the patch.
+
+template <class C, class T>
+__device__ __forceinline__ unsigned prefetch_records(const PatchArgs& a, const uint32_t* te, int ht) {
+  unsigned acc = 0u;
+#pragma unroll
+  for (int f = 0; f < C::M; ++f) {
+    const uint32_t w = te[2 * f + 1];
+    const uint32_t nnz = w & ~MASK_BIT;
+    const uint32_t vb = (nnz * (uint32_t)sizeof(T) + 7u) & ~7u;
+    const uint32_t rb = (vb + ((w & MASK_BIT) ? 8u * C::W : 2u * nnz) + 15u) & ~15u;
+    const uint8_t* rec = a.pool_in + 16ull * te[2 * f];
+    for (uint32_t o = (uint32_t)ht * 128u; o < rb; o += (uint32_t)C::NHT * 128u)
+      acc ^= *reinterpret_cast<const unsigned*>(rec + o);
+  }
+  return acc;
+}
+
+template <class C, class T>
+__device__ __forceinline__ unsigned prefetch_halo(const PatchArgs& a, int qn, int ht) {
+  // the four direct neighbours' strips (the diagonal corners are single values)
+  constexpr int BYTES = C::NSLOT * C::S * (int)sizeof(T);
+  constexpr int LINES = (BYTES + 127) / 128;
+  if (ht >= 4 * LINES) return 0u;
+  const int side = ht / LINES;
+  const int line = ht - side * LINES;
+  const int px = qn % a.npx;
+  const int py = qn / a.npx;
+  int nx = px, ny = py;
+  if (side < 2) nx = wrap(px + (side == 0 ? -1 : 1), a.npx);
+  else ny = wrap(py + (side == 2 ? -1 : 1), a.npx);
+  const uint8_t* strip = static_cast<const uint8_t*>(a.halo_in) +
+                         ((size_t)((nx + a.npx * ny) * 4 + side) * C::NSLOT) * C::S * sizeof(T);
+  return *reinterpret_cast<const unsigned*>(strip + line * 128);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// One step (time n -> n + 1) of patch blockIdx.x.  The LDS holds one patch
+// per CU, so the patch blockIdx.x + a.grid (a.grid = number of CUs) starts
+// later on a CU of the same XCD (blocks are placed round-robin over the 8
+// XCDs): its data is prefetched into that XCD's L2 meanwhile.
 template <class T, int P, int WAV, int SCH>
 __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(PatchArgs a) {
   using C = Cfg<T, P, WAV, SCH>;
-  LBMZ_PATCH_SHARED(C, T)
+  __shared__ Smem<C, T> sm;
   const int q = blockIdx.x;
   if (threadIdx.x == 0) {
     // Stop if an earlier launch of this batch failed (its input is the last
     // good state); a failure inside this launch lets every patch finish so
     // that the pool counter ends at the exact size the step needs.
     const bool stop = a.ctrl->abort != 0u && a.ctrl->abort_epoch < a.epoch;
-    s_misc[2] = stop ? 1u : 0u;
+    sm.misc[2] = stop ? 1u : 0u;
     if (!stop && q == 0) a.ctrl->top16[(a.epoch + 1u) % 3u] = 0ull;
   }
   __syncthreads();
-  if (s_misc[2] != 0u) return;
+  if (sm.misc[2] != 0u) return;
+  const int qn = q + a.grid;
+  const bool pf = (threadIdx.x >> 6) >= C::NPASS && a.grid > 0 && qn < a.npatch;
+  const int ht = (int)threadIdx.x - 64 * C::NPASS;
   LBMZ_MARK(0);
-  gather_ghosts<C, T, SCH>(a, q, s_ghost);
-  expand<C, T>(a.pool_in, a.table_in, q, s_tile, s_fi, s_w, s_words);
+  if constexpr (SCH == S_LBM) gather_lbm<C, T>(a, q, sm.tile, sm.ghost);
+  else gather_fv<C, T>(a, q, sm.ghost);
+  LBMZ_MARK(14);
+  expand_columns<C, T, WAV, false>(a, q, sm);
   LBMZ_MARK(1);
-  inverse_transform<C, T, WAV>(s_tile, a.levels);
-  LBMZ_MARK(2);
-  if constexpr (SCH == S_LBM) stencil_lbm<C, T>(a, s_tile, s_ghost);
-  else stencil_fv<C, T>(a, s_tile, s_ghost);
-  LBMZ_MARK(3);
-  forward_transform_threshold<C, T, WAV>(s_tile, a.levels, T(a.eps), a.rule);
-  LBMZ_MARK(4);
-  if (!compact<C, T>(a, q, s_tile, s_fi, s_w, s_misc)) return;
+  uint32_t pf_te = 0u;
+  if (pf && ht < 2 * C::M) pf_te = a.table_in[2 * (size_t)qn * C::M + ht];
+  unsigned pf_acc = 0u;
+  if (pf) pf_acc = prefetch_halo<C, T>(a, qn, ht);
+  row_pass<C, T, WAV, SCH, SCH == S_LBM ? ROW_INV_SHIFT : ROW_INV>(a, q, sm.tile, sm.ghost);
   __syncthreads();
-  LBMZ_MARK(5);
-  inverse_transform<C, T, WAV>(s_tile, a.levels);
-  LBMZ_MARK(6);
-  export_halo<C, T, SCH>(a, q, s_tile);
-  field_totals<C, T, WAV>(a.partials_out + (size_t)q * C::M, s_tile, s_red);
-  LBMZ_MARK(7);
+  LBMZ_MARK(2);
+  if constexpr (SCH == S_LBM) stencil_lbm<C, T>(a, sm.tile);
+  else stencil_fv<C, T>(a, sm.tile, sm.ghost);
+  LBMZ_MARK(3);
+  if (pf && ht < 2 * C::M) sm.pf_te[ht] = pf_te;
+  row_pass<C, T, WAV, SCH, ROW_FWD>(a, q, sm.tile, sm.ghost);
+  __syncthreads();
+  LBMZ_MARK(4);
+  if (pf) pf_acc ^= prefetch_records<C, T>(a, sm.pf_te, ht);
+  if (column_compact<C, T, WAV, true>(a, q, sm)) {
+    LBMZ_MARK(5);
+    row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
+    LBMZ_MARK(6);
+  }
+  if (pf_acc == 0x9e3779b9u && a.n < 0) sm.misc[3] = pf_acc;   // keeps the prefetch loads
 }
 
 // Auxiliary modes (state set-up, store restore, decompression).
 template <class T, int P, int WAV, int SCH>
 __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(PatchArgs a) {
   using C = Cfg<T, P, WAV, SCH>;
-  LBMZ_PATCH_SHARED(C, T)
+  __shared__ Smem<C, T> sm;
   const int q = blockIdx.x;
   const int px = q % a.npx;
   const int py = q / a.npx;
-  constexpr int pp = P;   // owned nodes per side
   if (a.mode == AUX_INIT || a.mode == AUX_COEF) {
     if (q == 0 && threadIdx.x == 0) a.ctrl->top16[(a.epoch + 1u) % 3u] = 0ull;
     for (int f = 0; f < C::M; ++f) {
@@ -787,33 +1177,29 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
         } else {
           v = static_cast<const T*>(a.coef_in)[((size_t)q * C::M + f) * C::NC + t];
         }
-        s_tile[f * C::FS + y * C::RS + x] = v;
+        sm.tile[field_base<C>(f) + y * C::RS + x] = v;
       }
     }
     __syncthreads();
-    if (a.mode == AUX_INIT) forward_transform_threshold<C, T, WAV>(s_tile, a.levels, T(a.eps), a.rule);
-    else threshold_pass<C, T>(s_tile, a.levels, T(a.eps), a.rule);
-    if (!compact<C, T>(a, q, s_tile, s_fi, s_w, s_misc)) return;
-    __syncthreads();
-    inverse_transform<C, T, WAV>(s_tile, a.levels);
-    export_halo<C, T, SCH>(a, q, s_tile);
-    field_totals<C, T, WAV>(a.partials_out + (size_t)q * C::M, s_tile, s_red);
+    bool ok;
+    if (a.mode == AUX_INIT) {
+      row_pass<C, T, WAV, SCH, ROW_FWD>(a, q, sm.tile, sm.ghost);
+      __syncthreads();
+      ok = column_compact<C, T, WAV, true>(a, q, sm);
+    } else {
+      ok = column_compact<C, T, WAV, false>(a, q, sm);
+    }
+    if (!ok) return;
+    row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
     return;
   }
-  expand<C, T>(a.pool_in, a.table_in, q, s_tile, s_fi, s_w, s_words);
-  inverse_transform<C, T, WAV>(s_tile, a.levels);
   if (a.mode == AUX_RESTORE) {
-    export_halo<C, T, SCH>(a, q, s_tile);
-    field_totals<C, T, WAV>(a.partials_out + (size_t)q * C::M, s_tile, s_red);
+    expand_columns<C, T, WAV, true>(a, q, sm);
+    totals_finish<C, T>(a.partials_out + (size_t)q * C::M, a.levels, sm);
+    row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
   } else {
-    T* out = static_cast<T*>(a.dense_out);
-    for (int f = 0; f < C::M; ++f) {
-      for (int t = threadIdx.x; t < pp * pp; t += C::NT) {
-        const int y = t / pp;
-        const int x = t - y * pp;
-        out[((size_t)f * a.n + (py * P + y)) * a.n + px * P + x] = s_tile[f * C::FS + y * C::RS + x];
-      }
-    }
+    expand_columns<C, T, WAV, false>(a, q, sm);
+    row_pass<C, T, WAV, SCH, ROW_INV_DENSE>(a, q, sm.tile, sm.ghost);
   }
 }
 
@@ -829,9 +1215,7 @@ hipError_t launch_patch_kernels(bool step, const PatchArgs& a, int npatch, hipSt
 
 template <class T, int P, int WAV, int SCH>
 constexpr size_t patch_lds_bytes() {
-  using C = Cfg<T, P, WAV, SCH>;
-  return sizeof(T) * (C::M * C::FS + 4 * C::NSLOT * C::GL) + 2 * C::M * C::W + 8 * C::M * C::W +
-         sizeof(FieldInfo) * C::M + 8 * C::NWAVES * C::M + 16;
+  return sizeof(Smem<Cfg<T, P, WAV, SCH>, T>);
 }
 
 }  // namespace lbmz

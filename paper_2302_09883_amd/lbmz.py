@@ -260,6 +260,16 @@ def _current_stream():
     return None
 
 
+def record_order(s: int) -> np.ndarray:
+    """Flat tile indices (y * s + x) in the record order of include/lbmz.h."""
+    p = s - 1 if s % 2 == 1 else s
+    yy, xx = np.meshgrid(np.arange(p), np.arange(p), indexing="ij")
+    parts = [(yy * s + xx).reshape(-1)]
+    if p != s:
+        parts += [np.arange(p) * s + p, p * s + np.arange(p), np.array([p * s + p])]
+    return np.concatenate(parts).astype(np.int64)
+
+
 def decode_records(table: np.ndarray, pool: bytes, s: int, dtype) -> np.ndarray:
     """Coefficient tiles ``[npatch, nfields, s, s]`` from a store (host-side reader).
 
@@ -270,7 +280,8 @@ def decode_records(table: np.ndarray, pool: bytes, s: int, dtype) -> np.ndarray:
     npatch, nf = table.shape[:2]
     nc = s * s
     w = (nc + 63) // 64
-    out = np.zeros((npatch, nf, nc), dtype=dtype)
+    order = record_order(s)
+    seq = np.zeros((npatch, nf, nc), dtype=dtype)
     buf = np.frombuffer(pool, dtype=np.uint8)
     for q in range(npatch):
         for f in range(nf):
@@ -282,8 +293,10 @@ def decode_records(table: np.ndarray, pool: bytes, s: int, dtype) -> np.ndarray:
             if word & MASK_BIT:
                 words = buf[off + vb:off + vb + 8 * w].view("<u8")
                 bits = np.unpackbits(words.view(np.uint8), bitorder="little")[:nc].astype(bool)
-                out[q, f, bits] = vals
+                seq[q, f, bits] = vals
             else:
                 idx = buf[off + vb:off + vb + 2 * nnz].view("<u2").astype(np.int64)
-                out[q, f, idx] = vals
+                seq[q, f, idx] = vals
+    out = np.zeros_like(seq)
+    out[:, :, order] = seq
     return out.reshape(npatch, nf, s, s)

@@ -74,7 +74,7 @@ def test_compaction_bit_exact(geom, eps, rule, zero_frac):
     table, pool = ctx.store()
     for q in range(g.npatch):
         for f in range(ctx.nfields):
-            rec = O.encode_record(np.ascontiguousarray(want[q, f]).reshape(-1))
+            rec = O.encode_record(want[q, f])
             nnz = int(np.count_nonzero(want[q, f] != 0))
             is_mask = O.record_layout(nnz, g.s * g.s, np.dtype(ctx.np_dtype).itemsize)[0]
             assert int(table[q, f, 1]) == nnz | (O.MASK_BIT if is_mask else 0), (q, f)

@@ -85,6 +85,23 @@ def test_threshold_is_strict_and_samples_survive():
     assert np.all(out2[samp] == 0.5) and np.all(out2[~samp] == 0)
 
 
+def test_record_order_is_a_core_then_rim_permutation():
+    for s in (9, 17, 65, 8, 32):
+        order = O.record_order(s)
+        assert np.array_equal(np.sort(order), np.arange(s * s))
+        p = s - 1 if s % 2 else s
+        # brute force: the owned block row by row comes first
+        k = 0
+        for y in range(p):
+            for x in range(p):
+                assert order[k] == y * s + x
+                k += 1
+        if p != s:
+            assert list(order[k:k + p]) == [y * s + p for y in range(p)]
+            assert list(order[k + p:k + 2 * p]) == [p * s + x for x in range(p)]
+            assert order[-1] == p * s + p
+
+
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_record_roundtrip_and_brute_force(dtype):
     tiles = random_coefficient_tiles((6, 65, 65), seed=3, dtype=dtype, zero_frac=0.3)
@@ -97,32 +114,35 @@ def test_record_roundtrip_and_brute_force(dtype):
     tiles[4] = 0
     tiles[4].reshape(-1)[:268] = -3.0
     tiles[5].reshape(-1)[17] = np.nan
+    order = O.record_order(65)
     for t in tiles:
-        flat = t.reshape(-1)
-        rec = O.encode_record(flat)
-        nnz = int(np.count_nonzero(flat != 0))
-        is_mask, vb, mb, rb = O.record_layout(nnz, flat.size, np.dtype(dtype).itemsize)
+        rec = O.encode_record(t)
+        seq = t.reshape(-1)[order]
+        nnz = int(np.count_nonzero(seq != 0))
+        is_mask, vb, mb, rb = O.record_layout(nnz, seq.size, np.dtype(dtype).itemsize)
         assert len(rec) == rb and rb % 16 == 0
         assert is_mask == (nnz >= 268)
         word = nnz | (O.MASK_BIT if is_mask else 0)
-        back = O.decode_record(rec, 0, word, flat.size, dtype)
-        keep = np.flatnonzero(flat != 0)             # brute force
-        assert np.array_equal(np.flatnonzero(back != 0) if not np.isnan(flat).any()
-                              else np.flatnonzero((back != 0) | np.isnan(back)), keep)
-        assert np.array_equal(back[keep], flat[keep], equal_nan=True)
+        back = O.decode_record(rec, 0, word, 65, dtype)
+        assert np.array_equal(back, np.where(t == 0, 0, t).astype(dtype), equal_nan=True)
+        keep = np.flatnonzero(seq != 0)             # brute force
         vals = np.frombuffer(rec, dtype=dtype, count=nnz)
-        assert np.array_equal(vals, flat[keep], equal_nan=True)
-        if not is_mask:
+        assert np.array_equal(vals, seq[keep], equal_nan=True)
+        if is_mask:
+            words = np.frombuffer(rec, dtype="<u8", count=(seq.size + 63) // 64, offset=vb)
+            bits = np.unpackbits(words.view(np.uint8), bitorder="little")[:seq.size]
+            assert np.array_equal(np.flatnonzero(bits), keep)
+        else:
             idx = np.frombuffer(rec, dtype="<u2", count=nnz, offset=vb)
             assert np.array_equal(idx, keep)
         assert all(b == 0 for b in rec[nnz * np.dtype(dtype).itemsize:vb])
 
 
 def test_negative_zero_is_not_stored():
-    flat = np.zeros(65 * 65, dtype=np.float32)
-    flat[5] = -0.0
-    flat[6] = 1.0
-    rec = O.encode_record(flat)
+    t = np.zeros((65, 65), dtype=np.float32)
+    t[0, 5] = -0.0
+    t[0, 6] = 1.0
+    rec = O.encode_record(t)
     assert len(rec) == 16                            # one value + one u16 index, padded
     assert np.frombuffer(rec, dtype="<u2", count=1, offset=8)[0] == 6
 
