@@ -34,7 +34,6 @@ struct PatchArgs {
   int n;             // grid cells per side
   int npx;           // patches per side
   int npatch;        // patches in the grid
-  int grid;          // workgroups resident at once (prefetch distance); 0 = no prefetch
   int levels;        // wavelet levels per dimension
   int rule;          // Rule
   double eps;        // threshold constant

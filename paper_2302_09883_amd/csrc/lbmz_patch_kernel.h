@@ -104,7 +104,6 @@ struct Smem {
   uint32_t ismask[C::M];
   uint32_t vb[C::M];
   uint32_t rb[C::M];
-  uint32_t pf_te[2 * C::M];              // offset-table entries of the next patch (prefetch)
   unsigned misc[4];
 };
 
@@ -392,21 +391,32 @@ __device__ __forceinline__ void threshold_column(T* v, int x, int L, T eps, int 
 }
 
 // S9 partial of one column of coefficients: trapezoid weights of the coarse
-// samples (1/2 on the tile ends for BL5/3), FP64, fixed order.  0 for a
-// detail column.
+// samples (1/2 on the tile ends for BL5/3), FP64, ascending y.  The level
+// count is uniform, so the branch on it is scalar and only the samples are
+// converted and added.  0 for a detail column.
+template <class C, class T, int LL = 1>
+__device__ __forceinline__ double samples_of_column(const T* v, int L) {
+  if constexpr (LL > C::LMAX) {
+    return 0.0;
+  } else {
+    if (L == LL) {
+      double acc = 0.0;
+#pragma unroll
+      for (int y = 0; y < C::S; y += (1 << LL)) {
+        const double w = (C::RIM && (y == 0 || y == C::S - 1)) ? 0.5 : 1.0;
+        acc += w * (double)v[y];
+      }
+      return acc;
+    }
+    return samples_of_column<C, T, LL + 1>(v, L);
+  }
+}
+
 template <class C, class T>
 __device__ __forceinline__ double column_sample_sum(const T* v, int x, int L) {
   if ((x & ((1 << L) - 1)) != 0) return 0.0;
-  double acc = 0.0;
-#pragma unroll
-  for (int y = 0; y < C::S; ++y) {
-    if (level_class<C::LMAX>(y) > L) {
-      const double w = (C::RIM && (y == 0 || y == C::S - 1)) ? 0.5 : 1.0;
-      acc += w * (double)v[y];
-    }
-  }
   const double wx = (C::RIM && (x == 0 || x == C::S - 1)) ? 0.5 : 1.0;
-  return wx * acc;
+  return wx * samples_of_column<C, T>(v, L);
 }
 
 // Waves 0..M-1 reduce the column partials of their field into sm.tot[f]; the
@@ -428,12 +438,23 @@ __device__ __forceinline__ void totals_partial(double part, Smem<C, T>& sm) {
 // (equation "conservation", per dimension), the trapezoid mass of the
 // reconstructed tile is 4^L times the coarse trapezoid mass of its samples,
 // whatever the thresholded details are.
-template <class C, class T>
-__device__ __forceinline__ void totals_finish(double* out, int L, Smem<C, T>& sm) {
+//
+// With CHECK, a non-finite total raises the abort flag: the forward lifting
+// carries every element into the coarse samples of its lines (each detail
+// enters at least one interior sample update at every level), so a
+// non-finite value anywhere in the transformed tile makes a sample, and
+// hence its field's total, non-finite.
+template <class C, class T, bool CHECK>
+__device__ __forceinline__ void totals_finish(const PatchArgs& a, double* out, int L, Smem<C, T>& sm) {
   const int tid = threadIdx.x;
   if (tid < C::M) {
     const double s = (double)(1 << L) * (double)(1 << L);
-    out[tid] = s * (sm.tot[tid] + (C::RIM ? sm.totface[tid] : 0.0));
+    const double t = s * (sm.tot[tid] + (C::RIM ? sm.totface[tid] : 0.0));
+    out[tid] = t;
+    if (CHECK && !(fabs(t) <= 0x1.fffffffffffffp+1023)) {
+      atomicOr(&a.ctrl->abort, ABORT_NONFINITE);
+      atomicMin(&a.ctrl->abort_epoch, a.epoch);
+    }
   }
 }
 
@@ -878,6 +899,7 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, Smem<C
 template <class C, class T, int WAV, bool FWD>
 __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C, T>& sm) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
+  static_assert(sizeof(sm.ghost) >= sizeof(T) * C::M * C::S, "shared-column staging does not fit");
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = wave_id();
@@ -893,37 +915,43 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C
     load_col<C>(v, sm.tile, field_base<C>(f), x);
     if constexpr (FWD) LF::fwd(v, L);
     threshold_column<C, T>(v, x, L, T(a.eps), a.rule);
-    // Non-finite detection: a scaled sum of magnitudes stays finite for any
-    // finite column and turns into Inf / NaN with any non-finite element.
+    if constexpr (!FWD) {
+      // Given coefficients: a scaled sum of magnitudes stays finite for any
+      // finite column and turns into Inf / NaN with any non-finite element.
+      // (After a forward transform the totals carry the same information.)
 #pragma unroll
-    for (int y = 0; y < C::S; ++y) mag = fma(fabs(v[y]), T(0x1p-64), mag);
+      for (int y = 0; y < C::S; ++y) mag = fma(fabs(v[y]), T(0x1p-64), mag);
+    }
     part = column_sample_sum<C, T>(v, x, L);
   }
-  if (__ballot(!(mag <= max_finite<T>())) != 0ull && lane == 0) {
-    atomicOr(&a.ctrl->abort, ABORT_NONFINITE);
-    atomicMin(&a.ctrl->abort_epoch, a.epoch);
+  if constexpr (!FWD) {
+    if (__ballot(!(mag <= max_finite<T>())) != 0ull && lane == 0) {
+      atomicOr(&a.ctrl->abort, ABORT_NONFINITE);
+      atomicMin(&a.ctrl->abort_epoch, a.epoch);
+    }
   }
   totals_partial<C, T>(part, sm);
   LBMZ_MARK(8);
 
-  // Counts: one ballot per owned row (and the shared row); the shared column
-  // is held by the lanes of wave M, one field per lane.
+  // Counts: one ballot per owned row (and the shared row), restricted to the
+  // lanes that hold a line by a scalar mask.  The shared-column wave parks
+  // its thresholded coefficients in the ghost buffer (unused from here on),
+  // where wave 0 counts them and the field waves store them.
+  T* rimc = sm.ghost;   // [field][y]
+  const unsigned long long actm = __ballot(act);
   if (wave < C::M) {
     int run = 0;
 #pragma unroll
-    for (int y = 0; y < C::P; ++y) run += __popcll(__ballot(act && v[y] != T(0)));
+    for (int y = 0; y < C::P; ++y) run += __popcll(__ballot(v[y] != T(0)) & actm);
     unsigned long long rowb = 0ull;
-    if constexpr (C::RIM) rowb = __ballot(act && v[C::P] != T(0));
+    if constexpr (C::RIM) rowb = __ballot(v[C::P] != T(0)) & actm;
     if (lane == 0) {
       sm.core_nnz[wave] = (unsigned)run;
       sm.rowbits[wave] = rowb;
     }
   } else if (C::RIM && wave == C::M && act) {
-    unsigned long long col = 0ull;
 #pragma unroll
-    for (int y = 0; y < C::P; ++y) col |= (v[y] != T(0) ? 1ull : 0ull) << y;
-    sm.colbits[f] = col;
-    sm.corner[f] = v[C::P] != T(0) ? 1u : 0u;
+    for (int y = 0; y < C::S; ++y) rimc[f * C::S + y] = v[y];
   }
   __syncthreads();
   LBMZ_MARK(9);
@@ -931,11 +959,25 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C
   // Record layouts (lane g of wave 0 for field g), offsets inside the patch
   // by a wave scan, and one allocation for the patch.
   if (wave == 0) {
+    unsigned long long mycol = 0ull;
+    uint32_t mycorner = 0u;
+    if constexpr (C::RIM) {
+      const int yy = lane < C::P ? lane : 0;
+#pragma unroll
+      for (int g = 0; g < C::M; ++g) {
+        const unsigned long long cb = __ballot(lane < C::P && rimc[g * C::S + yy] != T(0));
+        if (lane == g) mycol = cb;
+      }
+      if (lane < C::M) mycorner = rimc[lane * C::S + C::P] != T(0) ? 1u : 0u;
+    }
     uint32_t rb16 = 0;
     if (lane < C::M) {
       uint32_t nnz = sm.core_nnz[lane];
-      if constexpr (C::RIM)
-        nnz += (uint32_t)(__popcll(sm.colbits[lane]) + __popcll(sm.rowbits[lane])) + sm.corner[lane];
+      if constexpr (C::RIM) {
+        nnz += (uint32_t)(__popcll(mycol) + __popcll(sm.rowbits[lane])) + mycorner;
+        sm.colbits[lane] = mycol;
+        sm.corner[lane] = mycorner;
+      }
       const uint32_t ismask = (2u * nnz < 8u * C::W) ? 0u : 1u;
       const uint32_t vb = (nnz * (uint32_t)sizeof(T) + 7u) & ~7u;
       const uint32_t mb = ismask ? 8u * C::W : 2u * nnz;
@@ -968,8 +1010,9 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C
     a.table_out[2 * (q * C::M + tid) + 1] = sm.nnz[tid] | (sm.ismask[tid] ? MASK_BIT : 0u);
   }
 
-  // Stores: the rank of a kept coefficient is the count of kept ones in the
-  // rows before it plus the kept lanes below it in its row (mbcnt).
+  // Stores: the rank of a kept coefficient is the count of kept ones before
+  // it in record order (owned rows, shared column, shared row, corner); in a
+  // row, the kept lanes below it (mbcnt).
   if (wave < C::M) {
     uint8_t* rec = a.pool_out + 16ull * (base16 + sm.rel16[f]);
     T* vals = reinterpret_cast<T*>(rec);
@@ -980,7 +1023,7 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C
     int run = 0;
 #pragma unroll
     for (int y = 0; y < C::P; ++y) {
-      const unsigned long long b = __ballot(act && v[y] != T(0));
+      const unsigned long long b = __ballot(v[y] != T(0)) & actm;
       if (b != 0ull) {
         if (act && v[y] != T(0)) {
           const int rank = run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32),
@@ -1000,34 +1043,32 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C
       }
     }
     if constexpr (C::RIM) {
+      const unsigned long long col = sm.colbits[f];
       const unsigned long long rowb = sm.rowbits[f];
+      if (col != 0ull) {
+        // shared column, lane = y
+        const int yy = lane < C::P ? lane : 0;
+        const T c = rimc[f * C::S + yy];
+        if (lane < C::P && ((col >> yy) & 1ull)) {
+          const int rank = run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(col >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((unsigned)col, 0u));
+          vals[rank] = c;
+          if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + lane);
+        }
+      }
+      const int after_col = run + __popcll(col);
       if (act && v[C::P] != T(0)) {
-        const int rank = run + __popcll(sm.colbits[f]) + __popcll(rowb & below(x));
+        const int rank = after_col + __popcll(rowb & below(x));
         vals[rank] = v[C::P];
         if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + C::P + x);
       }
-    }
-    if (ismask && lane < C::CW) reinterpret_cast<unsigned long long*>(rec + sm.vb[f])[lane] = myw;
-  } else if (C::RIM && wave == C::M && act) {
-    uint8_t* rec = a.pool_out + 16ull * (base16 + sm.rel16[f]);
-    T* vals = reinterpret_cast<T*>(rec);
-    const bool ismask = sm.ismask[f] != 0u;
-    uint16_t* idx = reinterpret_cast<uint16_t*>(rec + sm.vb[f]);
-    const unsigned long long col = sm.colbits[f];
-    int rank = (int)sm.core_nnz[f];
-#pragma unroll
-    for (int y = 0; y < C::P; ++y) {
-      if ((col >> y) & 1ull) {
-        vals[rank] = v[y];
-        if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + y);
-        ++rank;
+      if (lane == 0 && sm.corner[f] != 0u) {
+        const int rank = after_col + __popcll(rowb);
+        vals[rank] = rimc[f * C::S + C::P];
+        if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + 2 * C::P);
       }
     }
-    if (sm.corner[f]) {
-      rank += __popcll(sm.rowbits[f]);
-      vals[rank] = v[C::P];
-      if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + 2 * C::P);
-    }
+    if (ismask && lane < C::CW) reinterpret_cast<unsigned long long*>(rec + sm.vb[f])[lane] = myw;
   }
   if (tid < C::M) {
     const int g = tid;
@@ -1046,7 +1087,7 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C
     const uint32_t mend = sm.vb[g] + (sm.ismask[g] ? 8u * C::W : 2u * sm.nnz[g]);
     for (uint32_t o = mend; o < sm.rb[g]; o += 2) *reinterpret_cast<uint16_t*>(rec + o) = 0;
   }
-  totals_finish<C, T>(a.partials_out + (size_t)q * C::M, L, sm);
+  totals_finish<C, T, FWD>(a, a.partials_out + (size_t)q * C::M, L, sm);
   LBMZ_MARK(11);
 
   // S8, column half: inverse of the thresholded column, back to LDS.
@@ -1059,55 +1100,10 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C
 }
 
 // ---------------------------------------------------------------------------
-// Prefetch of the next patch of a workgroup
-// ---------------------------------------------------------------------------
-// The helper waves (no line in the passes) touch the next patch's offset-table
-// entries, the cache lines of its records and its halo sources while the
-// current patch computes, so that its expansion finds them in L2.  The loaded
-// words are folded into one value that is consumed at the end of the patch.
-
-template <class C, class T>
-__device__ __forceinline__ unsigned prefetch_records(const PatchArgs& a, const uint32_t* te, int ht) {
-  unsigned acc = 0u;
-#pragma unroll
-  for (int f = 0; f < C::M; ++f) {
-    const uint32_t w = te[2 * f + 1];
-    const uint32_t nnz = w & ~MASK_BIT;
-    const uint32_t vb = (nnz * (uint32_t)sizeof(T) + 7u) & ~7u;
-    const uint32_t rb = (vb + ((w & MASK_BIT) ? 8u * C::W : 2u * nnz) + 15u) & ~15u;
-    const uint8_t* rec = a.pool_in + 16ull * te[2 * f];
-    for (uint32_t o = (uint32_t)ht * 128u; o < rb; o += (uint32_t)C::NHT * 128u)
-      acc ^= *reinterpret_cast<const unsigned*>(rec + o);
-  }
-  return acc;
-}
-
-template <class C, class T>
-__device__ __forceinline__ unsigned prefetch_halo(const PatchArgs& a, int qn, int ht) {
-  // the four direct neighbours' strips (the diagonal corners are single values)
-  constexpr int BYTES = C::NSLOT * C::S * (int)sizeof(T);
-  constexpr int LINES = (BYTES + 127) / 128;
-  if (ht >= 4 * LINES) return 0u;
-  const int side = ht / LINES;
-  const int line = ht - side * LINES;
-  const int px = qn % a.npx;
-  const int py = qn / a.npx;
-  int nx = px, ny = py;
-  if (side < 2) nx = wrap(px + (side == 0 ? -1 : 1), a.npx);
-  else ny = wrap(py + (side == 2 ? -1 : 1), a.npx);
-  const uint8_t* strip = static_cast<const uint8_t*>(a.halo_in) +
-                         ((size_t)((nx + a.npx * ny) * 4 + side) * C::NSLOT) * C::S * sizeof(T);
-  return *reinterpret_cast<const unsigned*>(strip + line * 128);
-}
-
-// ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
 
-// One step (time n -> n + 1) of patch blockIdx.x.  The LDS holds one patch
-// per CU, so the patch blockIdx.x + a.grid (a.grid = number of CUs) starts
-// later on a CU of the same XCD (blocks are placed round-robin over the 8
-// XCDs): its data is prefetched into that XCD's L2 meanwhile.
+// One step (time n -> n + 1) of patch blockIdx.x.
 template <class T, int P, int WAV, int SCH>
 __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(PatchArgs a) {
   using C = Cfg<T, P, WAV, SCH>;
@@ -1123,36 +1119,26 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(P
   }
   __syncthreads();
   if (sm.misc[2] != 0u) return;
-  const int qn = q + a.grid;
-  const bool pf = (threadIdx.x >> 6) >= C::NPASS && a.grid > 0 && qn < a.npatch;
-  const int ht = (int)threadIdx.x - 64 * C::NPASS;
   LBMZ_MARK(0);
   if constexpr (SCH == S_LBM) gather_lbm<C, T>(a, q, sm.tile, sm.ghost);
   else gather_fv<C, T>(a, q, sm.ghost);
   LBMZ_MARK(14);
   expand_columns<C, T, WAV, false>(a, q, sm);
   LBMZ_MARK(1);
-  uint32_t pf_te = 0u;
-  if (pf && ht < 2 * C::M) pf_te = a.table_in[2 * (size_t)qn * C::M + ht];
-  unsigned pf_acc = 0u;
-  if (pf) pf_acc = prefetch_halo<C, T>(a, qn, ht);
   row_pass<C, T, WAV, SCH, SCH == S_LBM ? ROW_INV_SHIFT : ROW_INV>(a, q, sm.tile, sm.ghost);
   __syncthreads();
   LBMZ_MARK(2);
   if constexpr (SCH == S_LBM) stencil_lbm<C, T>(a, sm.tile);
   else stencil_fv<C, T>(a, sm.tile, sm.ghost);
   LBMZ_MARK(3);
-  if (pf && ht < 2 * C::M) sm.pf_te[ht] = pf_te;
   row_pass<C, T, WAV, SCH, ROW_FWD>(a, q, sm.tile, sm.ghost);
   __syncthreads();
   LBMZ_MARK(4);
-  if (pf) pf_acc ^= prefetch_records<C, T>(a, sm.pf_te, ht);
   if (column_compact<C, T, WAV, true>(a, q, sm)) {
     LBMZ_MARK(5);
     row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
     LBMZ_MARK(6);
   }
-  if (pf_acc == 0x9e3779b9u && a.n < 0) sm.misc[3] = pf_acc;   // keeps the prefetch loads
 }
 
 // Auxiliary modes (state set-up, store restore, decompression).
@@ -1195,7 +1181,7 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
   }
   if (a.mode == AUX_RESTORE) {
     expand_columns<C, T, WAV, true>(a, q, sm);
-    totals_finish<C, T>(a.partials_out + (size_t)q * C::M, a.levels, sm);
+    totals_finish<C, T, false>(a, a.partials_out + (size_t)q * C::M, a.levels, sm);
     row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
   } else {
     expand_columns<C, T, WAV, false>(a, q, sm);

@@ -415,15 +415,6 @@ int lbmz_create(const lbmz_grid* grid, const lbmz_scheme* scheme, const lbmz_pat
     a.levels = c->levels;
     a.rule = c->rule;
     a.eps = c->eps;
-    // Workgroups resident at once: one per compute unit (the LDS holds one
-    // patch per CU); the step kernel prefetches the patch that many blocks
-    // ahead.  LBMZ_PREFETCH_DISTANCE overrides it (0 disables the prefetch).
-    int ncu = 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu <= 0)
-      ncu = c->npatch;
-    const char* env = getenv("LBMZ_PREFETCH_DISTANCE");
-    if (env) ncu = atoi(env);
-    a.grid = ncu < 0 ? 0 : ncu;
   }
   if (rc != LBMZ_OK) {
     // the message is lost with the context; callers get the code only

@@ -15,6 +15,7 @@ from .fields import (
     worked_example_field,
     random_signal,
     random_coefficient_tiles,
+    transport_gaussian,
 )
 
 __all__ = [
@@ -24,4 +25,5 @@ __all__ = [
     "worked_example_field",
     "random_signal",
     "random_coefficient_tiles",
+    "transport_gaussian",
 ]

@@ -132,3 +132,30 @@ def random_coefficient_tiles(shape, seed: int = 0, dtype=np.float32,
     out[zero] = 0.0
     out[zero & negz] = -0.0
     return out
+
+
+def transport_gaussian(n: int = 128, t: float = 0.0, vel=(0.9, 0.9), lo: float = -1.0,
+                       hi: float = 1.0) -> np.ndarray:
+    """The paper's transport test field ``[n, n]`` (float64) at time ``t``.
+
+    ``f(x, y, t) = 1 + exp(-30 ((x - alpha t)^2 + (y - beta t)^2))`` sampled at
+    the cell centres ``lo + (i + 1/2) h``, ``h = (hi - lo) / n``, of the
+    periodic square ``[lo, hi)^2``; the displaced centre is taken modulo the
+    period (minimum image).  ``t = 0`` is the initial state, ``t > 0`` the exact
+    solution of the transport equation with speed ``vel`` (Section 3.2,
+    transport simulation).  No random numbers.
+    """
+    side = hi - lo
+    h = side / n
+    c = lo + (np.arange(n, dtype=np.float64) + 0.5) * h
+
+    def wrapped(x):
+        return (x - lo) % side + lo if side > 0 else x
+
+    cx = wrapped(np.float64(vel[0]) * t)
+    cy = wrapped(np.float64(vel[1]) * t)
+    dx = c - cx
+    dx = dx - side * np.round(dx / side)
+    dy = c - cy
+    dy = dy - side * np.round(dy / side)
+    return 1.0 + np.exp(-30.0 * (dy[:, None] ** 2 + dx[None, :] ** 2))
