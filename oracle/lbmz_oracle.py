@@ -511,6 +511,60 @@ def fv_upwind_update(padded: np.ndarray, vel, cfl: float) -> np.ndarray:
     return out
 
 
+# Compressible Euler equations with the Rusanov (local Lax-Friedrichs) flux:
+# the scheme of equation "vf_scheme" with m = 4 conserved fields
+# W = (rho, rho u, rho v, E) and the physical flux
+# F(W).N = (rho un, rho u un + p Nx, rho v un + p Ny, (E + p) un),
+# un = u Nx + v Ny, p = (gamma - 1) (E - rho (u^2 + v^2) / 2).  The paper
+# leaves the flux of a system to the scheme (it uses a Godunov flux for its
+# shallow-water test); Rusanov is the first-order flux of the precision
+# workload.  The time step is dt = CFL h / s_max with s_max a bound of
+# |u| + c given with the scheme.
+
+def euler_physical_flux(w: np.ndarray, normal, gamma: float):
+    """``(F(W).N, un, c)`` for states ``w[4, ...]``."""
+    nx, ny = normal
+    rho, mx, my, e = w[0], w[1], w[2], w[3]
+    u = mx / rho
+    v = my / rho
+    p = (gamma - 1.0) * (e - 0.5 * rho * (u * u + v * v))
+    un = u * nx + v * ny
+    c = np.sqrt(gamma * p / rho)
+    f = np.stack([rho * un, mx * un + p * nx, my * un + p * ny, (e + p) * un])
+    return f, un, c
+
+
+def rusanov_flux(wl: np.ndarray, wr: np.ndarray, normal, gamma: float) -> np.ndarray:
+    """``Q(W_L, W_R, N) = (F(W_L).N + F(W_R).N) / 2 - lambda (W_R - W_L) / 2`` with
+    ``lambda = max(|un_L| + c_L, |un_R| + c_R)``."""
+    fl, unl, cl = euler_physical_flux(wl, normal, gamma)
+    fr, unr, cr = euler_physical_flux(wr, normal, gamma)
+    lam = np.maximum(np.abs(unl) + cl, np.abs(unr) + cr)
+    return 0.5 * (fl + fr) - 0.5 * lam * (wr - wl)
+
+
+def euler_rusanov_update(padded: np.ndarray, dt_over_h: float, gamma: float) -> np.ndarray:
+    """One step on a ghost-padded state ``[..., 4, h + 2, w + 2]`` (fields on
+    the third axis from the end), in the order of the transport-kernel
+    listing: start from ``W``, then for each direction ``k = 0..3`` subtract
+    ``dt/h * Q(W, W_{+N^k}, N^k)``."""
+    pf = np.moveaxis(padded, -3, 0)          # fields first
+    w = pf[..., 1:-1, 1:-1]
+    out = np.array(w, copy=True)
+    hh, ww = w.shape[-2], w.shape[-1]
+    for (nx, ny) in NORMALS:
+        nb = pf[..., 1 + ny:1 + ny + hh, 1 + nx:1 + nx + ww]
+        out = out - dt_over_h * rusanov_flux(w, nb, (nx, ny), gamma)
+    return np.moveaxis(out, 0, -3)
+
+
+def euler_conserved(rho, u, v, p, gamma: float) -> np.ndarray:
+    """Conserved fields ``[4, ...]`` from primitive ones."""
+    rho = np.asarray(rho, dtype=np.float64)
+    e = np.asarray(p, dtype=np.float64) / (gamma - 1.0) + 0.5 * rho * (np.asarray(u) ** 2 + np.asarray(v) ** 2)
+    return np.stack([rho, rho * u, rho * v, e])
+
+
 # D2Q9 velocity set and weights (numbering 0: rest, 1-4: axes, 5-8: diagonals).
 D2Q9_C = np.array([(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1),
                    (1, 1), (-1, 1), (-1, -1), (1, -1)], dtype=np.int64)
@@ -556,20 +610,23 @@ def d2q9_bgk_update(padded: np.ndarray, tau: float) -> np.ndarray:
 
 @dataclass(frozen=True)
 class Scheme:
-    kind: str                     # "fv_upwind" or "d2q9_bgk"
-    vel: tuple = (1.0, 0.5)
+    kind: str                     # "fv_upwind", "d2q9_bgk" or "euler_rusanov"
+    vel: tuple = (1.0, 0.5)       # FV: transport velocity; Euler: (s_max, -) bound of |u| + c
     cfl: float = 0.5
     tau: float = 0.6
+    gamma: float = 1.4
 
     @property
     def nfields(self) -> int:
-        return 9 if self.kind == "d2q9_bgk" else 1
+        return {"d2q9_bgk": 9, "euler_rusanov": 4}.get(self.kind, 1)
 
     def update(self, padded: np.ndarray) -> np.ndarray:
         if self.kind == "fv_upwind":
             return fv_upwind_update(padded, self.vel, self.cfl)
         if self.kind == "d2q9_bgk":
             return d2q9_bgk_update(padded, self.tau)
+        if self.kind == "euler_rusanov":
+            return euler_rusanov_update(padded, self.cfl / self.vel[0], self.gamma)
         raise ValueError(self.kind)
 
 
@@ -607,20 +664,34 @@ class CompressedRun:
     """
 
     def __init__(self, g: Geometry, scheme: Scheme, eps: float, rule: str = RULE_CAPPED,
-                 dtype=np.float64):
+                 dtype=np.float64, values: str = "f32"):
         self.g = g.validate()
         self.scheme = scheme
         self.eps = eps
         self.rule = rule
         self.dtype = np.dtype(dtype)
+        self.values = values
+        if values != "f32" and self.dtype != np.float32:
+            raise ValueError("narrow value formats store float32 coefficients")
         self.thr = threshold_table(g.s, g.levels, eps, rule, self.dtype)
         self.coef = None
+        self.kept = None          # threshold decisions of the stored coefficients
         self.steps = 0
 
     # -- compression of tiles ------------------------------------------------
     def compress_tiles(self, tiles: np.ndarray) -> np.ndarray:
+        """Forward transform, hard threshold and, for a narrow value format,
+        the stored (quantised) representation of the details."""
         c = forward_2d(tiles.astype(self.dtype), self.g.levels, self.g.wavelet)
-        return hard_threshold(c, self.thr)
+        return self._store_form(hard_threshold(c, self.thr))
+
+    def _store_form(self, c: np.ndarray) -> np.ndarray:
+        self.kept = c != 0
+        self.raw = c              # thresholded, before any quantisation
+        if self.values == "f32":
+            return c
+        from .lbmz_precision import quantize_tiles
+        return quantize_tiles(c, self.g.levels, self.values)
 
     def decompress_tiles(self, coef: np.ndarray | None = None) -> np.ndarray:
         c = self.coef if coef is None else coef
@@ -634,7 +705,7 @@ class CompressedRun:
 
     def set_coefficients(self, coef: np.ndarray, threshold: bool = True):
         c = np.asarray(coef, dtype=self.dtype)
-        self.coef = hard_threshold(c, self.thr) if threshold else c.copy()
+        self.coef = self._store_form(hard_threshold(c, self.thr) if threshold else c.copy())
 
     def grid(self) -> np.ndarray:
         """Decompressed global state ``[m, n, n]`` (owned nodes of every tile)."""
@@ -651,14 +722,26 @@ class CompressedRun:
 
     # -- measurements ----------------------------------------------------------
     def store(self):
+        if self.values != "f32":
+            from .lbmz_precision import encode_store_q
+            return encode_store_q(self.raw, self.g.levels, self.values)
         return encode_store(self.coef)
 
     def nnz(self) -> np.ndarray:
-        return np.count_nonzero(self.coef.reshape(self.coef.shape[0], self.coef.shape[1], -1) != 0,
-                                axis=-1)
+        """Per (patch, field): stored coefficients (float32 records) or kept
+        details (narrow records, whose samples are always stored)."""
+        k = self.kept.reshape(self.kept.shape[0], self.kept.shape[1], -1)
+        if self.values == "f32":
+            return np.count_nonzero(k, axis=-1)
+        from .lbmz_precision import subband_table
+        det = subband_table(self.g.s, self.g.levels).reshape(-1) != 0
+        return np.count_nonzero(k & det, axis=-1)
 
     def store_bytes(self) -> int:
         ncoef = self.g.s * self.g.s
+        if self.values != "f32":
+            from .lbmz_precision import store_bytes_q
+            return store_bytes_q(self.kept.astype(np.float32), self.g.levels, self.values)
         tot = 0
         for v in self.nnz().reshape(-1):
             tot += record_layout(int(v), ncoef, self.dtype.itemsize)[3]

@@ -16,6 +16,7 @@ from .fields import (
     random_signal,
     random_coefficient_tiles,
     transport_gaussian,
+    riemann_four_quadrants,
 )
 
 __all__ = [
@@ -26,4 +27,5 @@ __all__ = [
     "random_signal",
     "random_coefficient_tiles",
     "transport_gaussian",
+    "riemann_four_quadrants",
 ]

@@ -159,3 +159,31 @@ def transport_gaussian(n: int = 128, t: float = 0.0, vel=(0.9, 0.9), lo: float =
     dy = c - cy
     dy = dy - side * np.round(dy / side)
     return 1.0 + np.exp(-30.0 * (dy[:, None] ** 2 + dx[None, :] ** 2))
+
+
+def riemann_four_quadrants(n: int = 4096, seed: int = 0, gamma: float = 1.4,
+                           rho_range=(0.1, 1.5), p_range=(0.1, 1.5)):
+    """Four-quadrant Riemann problem of the compressible Euler equations.
+
+    Returns ``(W, states)``: the conserved fields ``W[4, n, n]`` (float64;
+    density, x and y momentum, total energy ``p / (gamma - 1)``, the gas at
+    rest) and the quadrant states ``[(rho, p)] * 4``.  Quadrant 1 is
+    ``x >= 1/2, y >= 1/2``, then counter-clockwise (2: x < 1/2, y >= 1/2;
+    3: x < 1/2, y < 1/2; 4: x >= 1/2, y < 1/2) with cell centres
+    ``(i + 1/2) / n`` of the periodic unit square.  Draw order: the four
+    densities uniform in ``rho_range``, then the four pressures uniform in
+    ``p_range``.
+    """
+    rng = np.random.default_rng(seed)
+    rho_q = rng.uniform(rho_range[0], rho_range[1], size=4)
+    p_q = rng.uniform(p_range[0], p_range[1], size=4)
+    c = (np.arange(n, dtype=np.float64) + 0.5) / n
+    right = c[None, :] >= 0.5
+    top = c[:, None] >= 0.5
+    quad = np.where(top, np.where(right, 0, 1), np.where(right, 3, 2))
+    rho = rho_q[quad]
+    p = p_q[quad]
+    w = np.zeros((4, n, n), dtype=np.float64)
+    w[0] = rho
+    w[3] = p / (gamma - 1.0)
+    return w, [(float(rho_q[k]), float(p_q[k])) for k in range(4)]
