@@ -68,15 +68,23 @@ typedef enum {
    * scheme): 9 populations with velocities (0,0) (1,0) (0,1) (-1,0) (0,-1)
    * (1,1) (-1,1) (-1,-1) (1,-1), weights 4/9, 1/9, 1/36; pull streaming then
    * collision with relaxation time tau; the stored state is post-collision. */
-  LBMZ_LBM_D2Q9_BGK = 1
+  LBMZ_LBM_D2Q9_BGK = 1,
+  /* Compressible Euler equations, four conserved fields (rho, rho u, rho v,
+   * E), scheme of equation "vf_scheme" with the Rusanov flux
+   * Q(W_L, W_R, N) = (F(W_L).N + F(W_R).N) / 2 - lambda (W_R - W_L) / 2,
+   * lambda = max(|u.N| + c) over both states, c = sqrt(gamma p / rho),
+   * p = (gamma - 1)(E - rho |u|^2 / 2); time step dt = cfl * h / vel[0] with
+   * vel[0] a bound of |u| + c given by the caller.  float32 only. */
+  LBMZ_EULER_RUSANOV = 2
 } lbmz_scheme_kind;
 
 typedef struct {
   lbmz_scheme_kind kind;
   lbmz_dtype dtype;   /* arithmetic and storage type of the state */
-  double vel[3];      /* FV: transport velocity (alpha, beta) */
-  double cfl;         /* FV: Courant number */
+  double vel[3];      /* FV: transport velocity (alpha, beta); Euler: vel[0] bounds |u| + c */
+  double cfl;         /* FV, Euler: Courant number */
   double tau;         /* LBM: relaxation time (> 1/2) */
+  double gamma;       /* Euler: ratio of specific heats (> 1) */
 } lbmz_scheme;
 
 typedef enum {
@@ -96,22 +104,37 @@ typedef enum {
  * never thresholded. */
 typedef enum { LBMZ_THR_CAPPED = 0, LBMZ_THR_CONSTANT = 1, LBMZ_THR_ACCUM = 2 } lbmz_thr_rule;
 
+/* How the surviving coefficients of a record are stored (the record layouts
+ * are given with the store access calls below).  The narrow formats need a
+ * float32 state: the coarse samples stay float32 -- by equation
+ * "conservation" they alone carry the tile's mass, so the stored mass is
+ * exact -- and the details are stored as IEEE binary16 or OCP E4M3 codes
+ * with one power-of-two float32 scale per subband and record. */
+typedef enum {
+  LBMZ_VALUES_F32 = 0,   /* every kept coefficient in the state's dtype */
+  LBMZ_VALUES_F16 = 1,   /* float32 samples, binary16 details */
+  LBMZ_VALUES_E4M3 = 2   /* float32 samples, E4M3 details */
+} lbmz_values;
+
 /* Patch decomposition: p[0] = p[1] = cells per patch side, a power of two
- * in {8, 16, 32, 64} dividing n.  p[2] is ignored. */
+ * in {8, 16, 32, 64} dividing n (32 or 64 for the narrow value formats).
+ * p[2] is ignored. */
 typedef struct {
   int p[3];
   lbmz_wavelet wavelet;
   lbmz_thr_rule rule;
+  lbmz_values values;
 } lbmz_patch;
 
 typedef struct {
   int64_t steps;          /* steps taken since the state was last set */
-  int64_t nnz_total;      /* stored coefficients over all records */
+  int64_t nnz_total;      /* sum of the offset-table counts (kept coefficients; kept
+                             details for the narrow value formats) */
   int64_t store_bytes;    /* record bytes + offset-table bytes of the current store */
   int64_t capacity_bytes; /* bytes allocated for one pool buffer */
   int64_t dense_bytes;    /* n[0] * n[1] * fields * sizeof(dtype) */
   double ratio;           /* dense_bytes / store_bytes */
-  int32_t nfields;        /* 1 (FV) or 9 (LBM) */
+  int32_t nfields;        /* 1 (FV), 9 (LBM) or 4 (Euler) */
   int32_t npatch;         /* patches in the grid */
   double totals[16];      /* FP64 per-field sums of the decompressed state: trapezoid
                              weights 1/2 on shared bordering nodes (bl53), else 1 */
@@ -173,15 +196,31 @@ int lbmz_decompress_field(lbmz_ctx* ctx, int field, void* dst, size_t bytes, int
 int lbmz_stats(lbmz_ctx* ctx, lbmz_stats_t* out);
 
 /* ---- compressed store access (checkpoint, parity tests) -------------------
- * Record layout of one (patch, field) tile of s x s coefficients, s = p + 1
- * (bl53) or p (Haar), in-place interleaved wavelet layout, index t = x + s*y:
- *   values of the non-zero coefficients in ascending t (dtype, little endian),
- *   zero padding to a multiple of 8 bytes, then either nnz u16 indices t
- *   (when 2 nnz < 8 W, W = ceil(s*s/64)) or W u64 mask words (bit t%64 of
- *   word t/64), zero padding to a multiple of 16 bytes.
+ * Record order of the s x s coefficients of one (patch, field) tile, s = p + 1
+ * (bl53) or p (Haar), in-place interleaved wavelet layout: the owned p x p
+ * block row by row (x fastest), then for bl53 the shared column x = p
+ * (y = 0..p-1), the shared row y = p (x = 0..p-1) and the corner (p, p).  The
+ * record index k of a coefficient is its position in this order; W =
+ * ceil(s*s/64) mask words cover all k.
+ * LBMZ_VALUES_F32 record: the kept (non-zero) coefficients in ascending k
+ *   (dtype, little endian), zero padding to a multiple of 8 bytes, then
+ *   either their u16 indices k (when 2 nnz < 8 W) or W u64 mask words (bit
+ *   k%64 of word k/64), zero padding to a multiple of 16 bytes.  The offset
+ *   table count is nnz.
+ * Narrow records (LBMZ_VALUES_F16 / E4M3): u64 OCC with bit b set when
+ *   subband b = cy (L + 1) + cx holds a kept detail (cx, cy: 0 for a sample
+ *   index, else the detail level, 1 = finest); one float32 scale 2^k per set
+ *   bit, in increasing b, where 2^k is the smallest power of two with
+ *   max |detail| <= 65504 (F16) or 448 (E4M3) times 2^k; zero pad to 8;
+ *   float32 samples of all SC x SC sample positions (SC = (s-1)/2^L + 1),
+ *   slot (y >> L) SC + (x >> L), zero or not; zero pad to 8; the kept
+ *   details' codes code(c / 2^k) in ascending k (2 or 1 bytes each, round to
+ *   nearest even); zero pad to 8; then the u16 indices k of the kept details
+ *   (when 2 ndet < 8 W) or W mask words over them; zero pad to 16.  The
+ *   offset-table count is ndet, the number of kept details.
  * Offset table: npatch * nfields entries of two u32, patch-major
  *   (patch index px + (n/p) py), field-minor: record offset in 16-byte units
- *   and nnz | (1u << 31 when the record is a bitmask).
+ *   and the count | (1u << 31 when the record is a bitmask).
  * Record placement in the pool is not canonical (any non-overlapping layout
  * is valid); the records themselves are. */
 

@@ -28,7 +28,7 @@ detail level, 1 = finest) of the thresholding; its index is
 ``b = cy * (L + 1) + cx``.  For every subband of a record that holds a kept
 detail, the scale is the power of two ``2**k`` with the smallest integer
 ``k`` such that ``max |c| <= FMT_MAX * 2**k`` (FMT_MAX = 65504 for f16, 448 for
-e4m3); a detail is stored as ``Q(c / 2**k)`` and read back as
+e4m3), raised to ``k = -126`` if smaller (a normal float32); a detail is stored as ``Q(c / 2**k)`` and read back as
 ``Q(c / 2**k) * 2**k`` (both scalings exact).
 
 Record of one (patch, field) tile in a narrow format (little-endian):
@@ -125,7 +125,8 @@ def dequantize(q: np.ndarray, fmt: str) -> np.ndarray:
 
 
 def pow2_scale(maxabs: float, fmt: str) -> np.float32:
-    """Smallest power of two ``2**k`` with ``maxabs <= FMT_MAX * 2**k`` (1 for 0)."""
+    """Smallest power of two ``2**k`` with ``maxabs <= FMT_MAX * 2**k``, with
+    ``k >= -126`` so that the scale is a normal float32 (1 for 0)."""
     m = float(maxabs)
     if m == 0.0:
         return np.float32(1.0)
@@ -133,9 +134,9 @@ def pow2_scale(maxabs: float, fmt: str) -> np.float32:
     k = int(np.floor(np.log2(m / fmax)))
     while m > fmax * 2.0 ** k:
         k += 1
-    while k > -149 and m <= fmax * 2.0 ** (k - 1):
+    while m <= fmax * 2.0 ** (k - 1):
         k -= 1
-    return np.float32(2.0 ** k)
+    return np.float32(2.0 ** max(k, -126))
 
 
 # ---------------------------------------------------------------------------

@@ -24,6 +24,9 @@ SOURCES = [
     "lbmz_inst_f32_lbm.hip",
     "lbmz_inst_f64_fv.hip",
     "lbmz_inst_f64_lbm.hip",
+    "lbmz_inst_f32_fv_q.hip",
+    "lbmz_inst_f32_lbm_q.hip",
+    "lbmz_inst_f32_euler.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

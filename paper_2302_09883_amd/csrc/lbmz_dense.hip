@@ -47,6 +47,31 @@ __global__ __launch_bounds__(256) void ref_fv_kernel(const T* __restrict__ win, 
 }
 
 template <class T>
+__global__ __launch_bounds__(256) void ref_euler_kernel(const T* __restrict__ win, T* __restrict__ wout, int n,
+                                                        PatchArgs a) {
+  const int x = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (x >= n || y >= n) return;
+  const size_t nn = (size_t)n * n;
+  const size_t c = (size_t)y * n + x;
+  const size_t e = (size_t)y * n + (x + 1) % n, w_ = (size_t)y * n + (x - 1 + n) % n;
+  const size_t no = (size_t)((y + 1) % n) * n + x, so = (size_t)((y - 1 + n) % n) * n + x;
+  T w[4], we[4], ww[4], wn[4], ws[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    w[f] = win[f * nn + c];
+    we[f] = win[f * nn + e];
+    ww[f] = win[f * nn + w_];
+    wn[f] = win[f * nn + no];
+    ws[f] = win[f * nn + so];
+  }
+  T o[4];
+  euler_node<T>(w, we, ww, wn, ws, T(a.gamma), T(a.dt_over_h), o);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) wout[f * nn + c] = o[f];
+}
+
+template <class T>
 __global__ __launch_bounds__(256) void equilibrium_kernel(const T* __restrict__ rho, const T* __restrict__ ux,
                                                           const T* __restrict__ uy, T* __restrict__ f, int n) {
   const size_t nn = (size_t)n * n;
@@ -95,6 +120,13 @@ hipError_t launch_reference_step(int dtype, int scheme, const void* in, void* ou
     else
       hipLaunchKernelGGL(ref_lbm_kernel<double>, grid, dim3(256), 0, s, static_cast<const double*>(in),
                          static_cast<double*>(out), n, a.omega);
+  } else if (scheme == S_EULER) {
+    if (dtype == 0)
+      hipLaunchKernelGGL(ref_euler_kernel<float>, grid, dim3(256), 0, s, static_cast<const float*>(in),
+                         static_cast<float*>(out), n, a);
+    else
+      hipLaunchKernelGGL(ref_euler_kernel<double>, grid, dim3(256), 0, s, static_cast<const double*>(in),
+                         static_cast<double*>(out), n, a);
   } else {
     if (dtype == 0)
       hipLaunchKernelGGL(ref_fv_kernel<float>, grid, dim3(256), 0, s, static_cast<const float*>(in),

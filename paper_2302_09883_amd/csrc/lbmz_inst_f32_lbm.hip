@@ -5,7 +5,7 @@ namespace lbmz {
 
 bool dispatch_f32_lbm(const KernelKey& k, int op, const PatchArgs* a, int npatch, hipStream_t s,
                        hipError_t* err, size_t* lds) {
-  if (k.dtype != 0 || k.scheme != S_LBM) return false;
+  if (k.dtype != 0 || k.scheme != S_LBM || k.vf != VF_F32) return false;
   if (k.p == 8 && k.wavelet == W_HAAR) {
     if (op == 0) *err = launch_patch_kernels<float, 8, W_HAAR, S_LBM>(true, *a, npatch, s);
     else if (op == 1) *err = launch_patch_kernels<float, 8, W_HAAR, S_LBM>(false, *a, npatch, s);

@@ -5,7 +5,7 @@ namespace lbmz {
 
 bool dispatch_f64_fv(const KernelKey& k, int op, const PatchArgs* a, int npatch, hipStream_t s,
                        hipError_t* err, size_t* lds) {
-  if (k.dtype != 1 || k.scheme != S_FV) return false;
+  if (k.dtype != 1 || k.scheme != S_FV || k.vf != VF_F32) return false;
   if (k.p == 8 && k.wavelet == W_HAAR) {
     if (op == 0) *err = launch_patch_kernels<double, 8, W_HAAR, S_FV>(true, *a, npatch, s);
     else if (op == 1) *err = launch_patch_kernels<double, 8, W_HAAR, S_FV>(false, *a, npatch, s);

@@ -7,8 +7,11 @@
 namespace lbmz {
 
 enum Wavelet : int { W_HAAR = 0, W_BL53 = 1 };
-enum SchemeKind : int { S_FV = 0, S_LBM = 1 };
+enum SchemeKind : int { S_FV = 0, S_LBM = 1, S_EULER = 2 };
 enum Rule : int { R_CAPPED = 0, R_CONSTANT = 1, R_ACCUM = 2 };
+// How the values of a record are stored: float32 (every kept coefficient), or
+// float32 samples plus binary16 / OCP E4M3 details with per-subband scales.
+enum ValueFormat : int { VF_F32 = 0, VF_F16 = 1, VF_E4M3 = 2 };
 
 // Modes of the auxiliary (not time-critical) patch kernel.
 enum AuxMode : int {
@@ -42,6 +45,7 @@ struct PatchArgs {
   double cp[4];      // FV: max(a.N^k, 0)
   double cm[4];      // FV: min(a.N^k, 0)
   double omega;      // LBM: 1 / tau
+  double gamma;      // Euler: ratio of specific heats
   // store, time n
   const uint8_t* pool_in;
   const uint32_t* table_in;
@@ -67,6 +71,7 @@ struct KernelKey {
   int p;       // cells per patch side
   int wavelet; // Wavelet
   int scheme;  // SchemeKind
+  int vf;      // ValueFormat
 };
 
 // Launch the fused step kernel (time n -> n + 1) or the auxiliary kernel.

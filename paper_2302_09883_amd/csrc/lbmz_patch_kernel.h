@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lbmz_internal.h"
 
 namespace lbmz {
@@ -47,7 +49,7 @@ struct D2Q9 {
 // gather so that streaming in y becomes a fixed row offset.
 template <int SCH, int S, int RS>
 struct TileLayout {
-  static constexpr int M = (SCH == S_LBM) ? 9 : 1;
+  static constexpr int M = (SCH == S_LBM) ? 9 : (SCH == S_EULER ? 4 : 1);
   static constexpr int lo(int f) { return (SCH == S_LBM && D2Q9::CY[f] == 1) ? 1 : 0; }
   static constexpr int hi(int f) { return (SCH == S_LBM && D2Q9::CY[f] == -1) ? 1 : 0; }
   static constexpr int start(int f) {
@@ -65,7 +67,7 @@ struct Cfg {
   static constexpr bool RIM = (WAV == W_BL53);              // tiles carry the shared line P
   static constexpr int S = RIM ? P + 1 : P;                 // tile nodes per side
   static constexpr int RS = (S & 1) ? S : S + 1;            // LDS row stride (odd)
-  static constexpr int M = (SCH == S_LBM) ? 9 : 1;          // fields
+  static constexpr int M = (SCH == S_LBM) ? 9 : (SCH == S_EULER ? 4 : 1);   // fields
   static constexpr int NC = S * S;                          // coefficients per field
   static constexpr int W = (NC + 63) / 64;                  // mask words per record
   static constexpr int CW = P * P / 64;                     // mask words of the owned block
@@ -73,7 +75,7 @@ struct Cfg {
   static constexpr int NSLOT = (SCH == S_LBM) ? 3 : M;      // fields crossing one side
   static constexpr int LO = RIM ? 1 : 0;                    // first line a neighbour needs
   static constexpr int HI = P - 1;                          // last line a neighbour needs
-  static constexpr int NT = (SCH == S_LBM) ? 1024 : 256;    // threads per workgroup
+  static constexpr int NT = (SCH == S_LBM) ? 1024 : (SCH == S_EULER ? 512 : 256);   // threads per workgroup
   static constexpr int NWAVES = NT / 64;
   static constexpr int J = ilog2c(P);
   static constexpr int LMAX = RIM ? J - 1 : J;
@@ -89,7 +91,22 @@ struct Cfg {
 };
 
 // Shared memory of the patch kernels.
-template <class C, class T>
+// Scratch of the narrow value formats (per-subband maxima and scale
+// exponents, record section offsets, mask-word prefix counts).
+template <class C>
+struct NarrowLds {
+  static constexpr int NB = (C::LMAX + 1) * (C::LMAX + 1);   // subbands, index cy * (L + 1) + cx
+  float smax[C::M][NB];                  // max |kept detail| per subband, owned lines
+  float rmax[C::M][C::LMAX + 1];         // the same for the shared column (x class 0), by y class
+  unsigned long long occ[C::M];          // subbands holding a kept detail
+  signed char kexp[C::M][NB];            // scale 2^kexp of each subband
+  uint32_t hb[C::M];                     // byte offset of the samples in the record
+  uint32_t sb[C::M];                     // byte offset of the detail values
+  uint16_t wpre[C::M][C::W + 1];         // bitmask records: set bits before each word
+};
+struct NoLds {};
+
+template <class C, class T, int VF = VF_F32>
 struct Smem {
   T tile[C::TILE];
   T ghost[4 * C::NSLOT * C::S];          // D2Q9: W/E strips (x shift); FV: W/E/S/N strips
@@ -105,6 +122,7 @@ struct Smem {
   uint32_t vb[C::M];
   uint32_t rb[C::M];
   unsigned misc[4];
+  typename std::conditional<VF == VF_F32, NoLds, NarrowLds<C>>::type nq;
 };
 
 // ---------------------------------------------------------------------------
@@ -421,8 +439,8 @@ __device__ __forceinline__ double column_sample_sum(const T* v, int x, int L) {
 
 // Waves 0..M-1 reduce the column partials of their field into sm.tot[f]; the
 // shared-column wave stores one partial per lane (field) in sm.totface.
-template <class C, class T>
-__device__ __forceinline__ void totals_partial(double part, Smem<C, T>& sm) {
+template <class C, class T, class SM>
+__device__ __forceinline__ void totals_partial(double part, SM& sm) {
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
   if (wave < C::M) {
@@ -444,8 +462,8 @@ __device__ __forceinline__ void totals_partial(double part, Smem<C, T>& sm) {
 // enters at least one interior sample update at every level), so a
 // non-finite value anywhere in the transformed tile makes a sample, and
 // hence its field's total, non-finite.
-template <class C, class T, bool CHECK>
-__device__ __forceinline__ void totals_finish(const PatchArgs& a, double* out, int L, Smem<C, T>& sm) {
+template <class C, class T, bool CHECK, class SM>
+__device__ __forceinline__ void totals_finish(const PatchArgs& a, double* out, int L, SM& sm) {
   const int tid = threadIdx.x;
   if (tid < C::M) {
     const double s = (double)(1 << L) * (double)(1 << L);
@@ -706,6 +724,92 @@ __device__ __forceinline__ void stencil_fv(const PatchArgs& a, T* tile, const T*
   __syncthreads();
 }
 
+// Compressible Euler with the Rusanov flux: W = (rho, rho u, rho v, E),
+// F(W).N = (rho un, rho u un + p Nx, rho v un + p Ny, (E + p) un),
+// Q(W_L, W_R, N) = (F(W_L).N + F(W_R).N) / 2 - lambda (W_R - W_L) / 2 with
+// lambda = max(|un_L| + c_L, |un_R| + c_R), applied as in equation
+// "vf_scheme" in the direction order +x, -x, +y, -y.
+template <class T>
+__device__ __forceinline__ void euler_prim(const T* w, T gamma, T& u, T& v, T& p, T& c) {
+  const T inv = T(1) / w[0];
+  u = w[1] * inv;
+  v = w[2] * inv;
+  p = (gamma - T(1)) * (w[3] - T(0.5) * w[0] * (u * u + v * v));
+  c = sqrt(gamma * p * inv);
+}
+
+template <class T, int NX, int NY>
+__device__ __forceinline__ void euler_face(const T* wl, T ul, T vl, T pl, T cl, const T* wr, T gamma, T r,
+                                           T* o) {
+  T ur, vr, pr, cr;
+  euler_prim<T>(wr, gamma, ur, vr, pr, cr);
+  const T unl = ul * T(NX) + vl * T(NY);
+  const T unr = ur * T(NX) + vr * T(NY);
+  const T lam = fmax(fabs(unl) + cl, fabs(unr) + cr);
+  const T fl[4] = {wl[0] * unl, wl[1] * unl + pl * T(NX), wl[2] * unl + pl * T(NY), (wl[3] + pl) * unl};
+  const T fr[4] = {wr[0] * unr, wr[1] * unr + pr * T(NX), wr[2] * unr + pr * T(NY), (wr[3] + pr) * unr};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[k] = o[k] - r * (T(0.5) * (fl[k] + fr[k]) - T(0.5) * lam * (wr[k] - wl[k]));
+}
+
+// One Euler update of a node from its state and its four neighbours.
+template <class T>
+__device__ __forceinline__ void euler_node(const T* w, const T* we, const T* ww, const T* wn, const T* ws,
+                                           T gamma, T r, T* o) {
+  T u, v, p, c;
+  euler_prim<T>(w, gamma, u, v, p, c);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[k] = w[k];
+  euler_face<T, 1, 0>(w, u, v, p, c, we, gamma, r, o);
+  euler_face<T, -1, 0>(w, u, v, p, c, ww, gamma, r, o);
+  euler_face<T, 0, 1>(w, u, v, p, c, wn, gamma, r, o);
+  euler_face<T, 0, -1>(w, u, v, p, c, ws, gamma, r, o);
+}
+
+template <class C, class T>
+__device__ __forceinline__ void stencil_euler(const PatchArgs& a, T* tile, const T* ghost) {
+  static_assert(C::M == 4, "four conserved fields");
+  const T r = T(a.dt_over_h);
+  const T gamma = T(a.gamma);
+  T res[4][C::NPER];
+#pragma unroll
+  for (int k = 0; k < C::NPER; ++k) {
+    const int t = threadIdx.x + k * C::NT;
+    if (t < C::NC) {
+      const int y = t / C::S;
+      const int x = t - y * C::S;
+      T w[4], we[4], ww[4], wn[4], ws[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const T* tf = tile + C::Lay::fb(f);
+        const T* g = ghost + f * C::S;
+        w[f] = tf[y * C::RS + x];
+        we[f] = (x + 1 < C::S) ? tf[y * C::RS + x + 1] : g[(1 * C::NSLOT) * C::S + y];
+        ww[f] = (x >= 1) ? tf[y * C::RS + x - 1] : g[(0 * C::NSLOT) * C::S + y];
+        wn[f] = (y + 1 < C::S) ? tf[(y + 1) * C::RS + x] : g[(3 * C::NSLOT) * C::S + x];
+        ws[f] = (y >= 1) ? tf[(y - 1) * C::RS + x] : g[(2 * C::NSLOT) * C::S + x];
+      }
+      T o[4];
+      euler_node<T>(w, we, ww, wn, ws, gamma, r, o);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) res[f][k] = o[f];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+#pragma unroll
+    for (int k = 0; k < C::NPER; ++k) {
+      const int t = threadIdx.x + k * C::NT;
+      if (t < C::NC) {
+        const int y = t / C::S;
+        tile[C::Lay::fb(f) + y * C::RS + (t - y * C::S)] = res[f][k];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Optional per-phase wall-clock marks of the step kernel (profiling builds
 // compiled with -DLBMZ_PHASE_CLOCK; the product build has none).
@@ -731,8 +835,8 @@ static __device__ unsigned long long lbmz_phase_clock[4096 * 16];
 // Index-list records (sparse) are scattered into a zeroed LDS tile first.
 // With TOT, the S9 totals of the stored coefficients are taken on the way.
 
-template <class C, class T, int WAV, bool TOT>
-__device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, Smem<C, T>& sm) {
+template <class C, class T, int WAV, bool TOT, class SM>
+__device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -896,8 +1000,8 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, Smem<C
 // Returns false (uniformly) when the pool overflowed; the records are then
 // not written and the host replays the step with a larger pool.
 
-template <class C, class T, int WAV, bool FWD>
-__device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C, T>& sm) {
+template <class C, class T, int WAV, bool FWD, class SM>
+__device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
   static_assert(sizeof(sm.ghost) >= sizeof(T) * C::M * C::S, "shared-column staging does not fit");
   const int tid = threadIdx.x;
@@ -1099,15 +1203,33 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, Smem<C
   return true;
 }
 
+}  // namespace lbmz
+
+#include "lbmz_patch_narrow.h"
+
+namespace lbmz {
+
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
 
+template <class C, class T, int WAV, bool TOT, int VF, class SM>
+__device__ __forceinline__ void expand_any(const PatchArgs& a, int q, SM& sm) {
+  if constexpr (VF == VF_F32) expand_columns<C, T, WAV, TOT>(a, q, sm);
+  else expand_columns_q<C, T, WAV, TOT, VF>(a, q, sm);
+}
+
+template <class C, class T, int WAV, bool FWD, int VF, class SM>
+__device__ __forceinline__ bool compact_any(const PatchArgs& a, int q, SM& sm) {
+  if constexpr (VF == VF_F32) return column_compact<C, T, WAV, FWD>(a, q, sm);
+  else return column_compact_q<C, T, WAV, FWD, VF>(a, q, sm);
+}
+
 // One step (time n -> n + 1) of patch blockIdx.x.
-template <class T, int P, int WAV, int SCH>
+template <class T, int P, int WAV, int SCH, int VF = VF_F32>
 __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(PatchArgs a) {
   using C = Cfg<T, P, WAV, SCH>;
-  __shared__ Smem<C, T> sm;
+  __shared__ Smem<C, T, VF> sm;
   const int q = blockIdx.x;
   if (threadIdx.x == 0) {
     // Stop if an earlier launch of this batch failed (its input is the last
@@ -1123,18 +1245,19 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(P
   if constexpr (SCH == S_LBM) gather_lbm<C, T>(a, q, sm.tile, sm.ghost);
   else gather_fv<C, T>(a, q, sm.ghost);
   LBMZ_MARK(14);
-  expand_columns<C, T, WAV, false>(a, q, sm);
+  expand_any<C, T, WAV, false, VF>(a, q, sm);
   LBMZ_MARK(1);
   row_pass<C, T, WAV, SCH, SCH == S_LBM ? ROW_INV_SHIFT : ROW_INV>(a, q, sm.tile, sm.ghost);
   __syncthreads();
   LBMZ_MARK(2);
   if constexpr (SCH == S_LBM) stencil_lbm<C, T>(a, sm.tile);
+  else if constexpr (SCH == S_EULER) stencil_euler<C, T>(a, sm.tile, sm.ghost);
   else stencil_fv<C, T>(a, sm.tile, sm.ghost);
   LBMZ_MARK(3);
   row_pass<C, T, WAV, SCH, ROW_FWD>(a, q, sm.tile, sm.ghost);
   __syncthreads();
   LBMZ_MARK(4);
-  if (column_compact<C, T, WAV, true>(a, q, sm)) {
+  if (compact_any<C, T, WAV, true, VF>(a, q, sm)) {
     LBMZ_MARK(5);
     row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
     LBMZ_MARK(6);
@@ -1142,10 +1265,10 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(P
 }
 
 // Auxiliary modes (state set-up, store restore, decompression).
-template <class T, int P, int WAV, int SCH>
+template <class T, int P, int WAV, int SCH, int VF = VF_F32>
 __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(PatchArgs a) {
   using C = Cfg<T, P, WAV, SCH>;
-  __shared__ Smem<C, T> sm;
+  __shared__ Smem<C, T, VF> sm;
   const int q = blockIdx.x;
   const int px = q % a.npx;
   const int py = q / a.npx;
@@ -1171,37 +1294,37 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
     if (a.mode == AUX_INIT) {
       row_pass<C, T, WAV, SCH, ROW_FWD>(a, q, sm.tile, sm.ghost);
       __syncthreads();
-      ok = column_compact<C, T, WAV, true>(a, q, sm);
+      ok = compact_any<C, T, WAV, true, VF>(a, q, sm);
     } else {
-      ok = column_compact<C, T, WAV, false>(a, q, sm);
+      ok = compact_any<C, T, WAV, false, VF>(a, q, sm);
     }
     if (!ok) return;
     row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
     return;
   }
   if (a.mode == AUX_RESTORE) {
-    expand_columns<C, T, WAV, true>(a, q, sm);
+    expand_any<C, T, WAV, true, VF>(a, q, sm);
     totals_finish<C, T, false>(a, a.partials_out + (size_t)q * C::M, a.levels, sm);
     row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
   } else {
-    expand_columns<C, T, WAV, false>(a, q, sm);
+    expand_any<C, T, WAV, false, VF>(a, q, sm);
     row_pass<C, T, WAV, SCH, ROW_INV_DENSE>(a, q, sm.tile, sm.ghost);
   }
 }
 
-template <class T, int P, int WAV, int SCH>
+template <class T, int P, int WAV, int SCH, int VF = VF_F32>
 hipError_t launch_patch_kernels(bool step, const PatchArgs& a, int npatch, hipStream_t s) {
   using C = Cfg<T, P, WAV, SCH>;
   if (step)
-    hipLaunchKernelGGL((patch_step_kernel<T, P, WAV, SCH>), dim3(npatch), dim3(C::NT), 0, s, a);
+    hipLaunchKernelGGL((patch_step_kernel<T, P, WAV, SCH, VF>), dim3(npatch), dim3(C::NT), 0, s, a);
   else
-    hipLaunchKernelGGL((patch_aux_kernel<T, P, WAV, SCH>), dim3(npatch), dim3(C::NT), 0, s, a);
+    hipLaunchKernelGGL((patch_aux_kernel<T, P, WAV, SCH, VF>), dim3(npatch), dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
 
-template <class T, int P, int WAV, int SCH>
+template <class T, int P, int WAV, int SCH, int VF = VF_F32>
 constexpr size_t patch_lds_bytes() {
-  return sizeof(Smem<Cfg<T, P, WAV, SCH>, T>);
+  return sizeof(Smem<Cfg<T, P, WAV, SCH>, T, VF>);
 }
 
 }  // namespace lbmz

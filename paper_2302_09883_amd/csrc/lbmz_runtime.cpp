@@ -26,11 +26,16 @@ bool dispatch_f32_fv(const KernelKey&, int, const PatchArgs*, int, hipStream_t, 
 bool dispatch_f32_lbm(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
 bool dispatch_f64_fv(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
 bool dispatch_f64_lbm(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
+bool dispatch_f32_fv_q(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
+bool dispatch_f32_lbm_q(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
+bool dispatch_f32_euler(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
 
 static bool dispatch(const KernelKey& k, int op, const PatchArgs* a, int npatch, hipStream_t s,
                      hipError_t* err, size_t* lds) {
   return dispatch_f32_fv(k, op, a, npatch, s, err, lds) || dispatch_f32_lbm(k, op, a, npatch, s, err, lds) ||
-         dispatch_f64_fv(k, op, a, npatch, s, err, lds) || dispatch_f64_lbm(k, op, a, npatch, s, err, lds);
+         dispatch_f64_fv(k, op, a, npatch, s, err, lds) || dispatch_f64_lbm(k, op, a, npatch, s, err, lds) ||
+         dispatch_f32_fv_q(k, op, a, npatch, s, err, lds) || dispatch_f32_lbm_q(k, op, a, npatch, s, err, lds) ||
+         dispatch_f32_euler(k, op, a, npatch, s, err, lds);
 }
 
 hipError_t launch_step(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s) {
@@ -63,6 +68,7 @@ struct lbmz_ctx {
   int dtype = 0;
   size_t esize = 4;
   int n = 0, p = 0, npx = 0, npatch = 0, s = 0, levels = 0, wavelet = 0, rule = 0, scheme = 0;
+  int vf = VF_F32;   // ValueFormat of the records
   int nfields = 1, nslot = 1;
   double eps = 0.0;
   KernelKey key{};
@@ -126,7 +132,33 @@ int64_t record_bytes(const lbmz_ctx* c, int64_t nnz, bool* is_mask) {
   return align_up(vb + (mask ? 8 * w : 2 * nnz), 16);
 }
 
+// Narrow records: samples per tile, bytes per detail code, and the section
+// offsets of a record with ndet kept details and nocc occupied subbands.
+int64_t narrow_samples(const lbmz_ctx* c) {
+  const int64_t sc = ((c->s - 1) >> c->levels) + 1;
+  return sc * sc;
+}
+int64_t narrow_code_bytes(const lbmz_ctx* c) { return c->vf == VF_F16 ? 2 : 1; }
+struct NarrowLayout {
+  bool mask;
+  int64_t hb, sb, vb, rb;
+};
+NarrowLayout narrow_layout(const lbmz_ctx* c, int64_t ndet, int64_t nocc) {
+  NarrowLayout l;
+  const int64_t w = nwords(c);
+  l.mask = !(2 * ndet < 8 * w);
+  l.hb = align_up(8 + 4 * nocc, 8);
+  l.sb = l.hb + align_up(4 * narrow_samples(c), 8);
+  l.vb = l.sb + align_up(ndet * narrow_code_bytes(c), 8);
+  l.rb = align_up(l.vb + (l.mask ? 8 * w : 2 * ndet), 16);
+  return l;
+}
+
 int64_t worst_store_bytes(const lbmz_ctx* c) {
+  if (c->vf != VF_F32) {
+    const int64_t nb = (int64_t)(c->levels + 1) * (c->levels + 1);
+    return narrow_layout(c, ncoef(c), nb - 1).rb * c->nfields * c->npatch;
+  }
   return record_bytes(c, ncoef(c), nullptr) * c->nfields * c->npatch;
 }
 
@@ -329,19 +361,27 @@ int validate_common(const lbmz_grid* g, const lbmz_scheme* sc, lbmz_ctx* c) {
     if (!(sc->cfl > 0.0) || !std::isfinite(sc->cfl)) return fail(c, LBMZ_EINVAL, "cfl must be > 0");
   } else if (sc->kind == LBMZ_LBM_D2Q9_BGK) {
     if (!(sc->tau > 0.5) || !std::isfinite(sc->tau)) return fail(c, LBMZ_EINVAL, "tau must be > 1/2");
+  } else if (sc->kind == LBMZ_EULER_RUSANOV) {
+    if (!(sc->vel[0] > 0.0) || !std::isfinite(sc->vel[0]))
+      return fail(c, LBMZ_EINVAL, "Euler: vel[0] (the bound of |u| + c) must be > 0");
+    if (!(sc->cfl > 0.0) || !std::isfinite(sc->cfl)) return fail(c, LBMZ_EINVAL, "cfl must be > 0");
+    if (!(sc->gamma > 1.0) || !std::isfinite(sc->gamma)) return fail(c, LBMZ_EINVAL, "gamma must be > 1");
   } else {
     return fail(c, LBMZ_EINVAL, "unknown scheme kind %d", (int)sc->kind);
   }
   c->n = (int)g->n[0];
   c->dtype = sc->dtype == LBMZ_F64 ? 1 : 0;
   c->esize = c->dtype ? 8 : 4;
-  c->scheme = sc->kind == LBMZ_LBM_D2Q9_BGK ? S_LBM : S_FV;
-  c->nfields = c->scheme == S_LBM ? 9 : 1;
-  c->nslot = c->scheme == S_LBM ? 3 : 1;
+  c->scheme = sc->kind == LBMZ_LBM_D2Q9_BGK ? S_LBM : (sc->kind == LBMZ_EULER_RUSANOV ? S_EULER : S_FV);
+  c->nfields = c->scheme == S_LBM ? 9 : (c->scheme == S_EULER ? 4 : 1);
+  c->nslot = c->scheme == S_LBM ? 3 : c->nfields;
   PatchArgs& a = c->base;
   memset(&a, 0, sizeof a);
   a.n = c->n;
-  if (c->scheme == S_FV) {
+  if (c->scheme == S_EULER) {
+    a.dt_over_h = sc->cfl / sc->vel[0];
+    a.gamma = sc->gamma;
+  } else if (c->scheme == S_FV) {
     const double vmax = std::max(std::fabs(sc->vel[0]), std::fabs(sc->vel[1]));
     a.dt_over_h = sc->cfl / vmax;
     const double an[4] = {sc->vel[0], -sc->vel[0], sc->vel[1], -sc->vel[1]};
@@ -394,7 +434,12 @@ int lbmz_create(const lbmz_grid* grid, const lbmz_scheme* scheme, const lbmz_pat
       c->levels = levels;
       c->rule = patch->rule == LBMZ_THR_CAPPED ? R_CAPPED : patch->rule == LBMZ_THR_ACCUM ? R_ACCUM : R_CONSTANT;
       c->eps = eps;
-      c->key = KernelKey{c->dtype, p, c->wavelet, c->scheme};
+      if (patch->values != LBMZ_VALUES_F32 && patch->values != LBMZ_VALUES_F16 && patch->values != LBMZ_VALUES_E4M3)
+        rc = fail(c, LBMZ_EINVAL, "unknown value format");
+      else if (patch->values != LBMZ_VALUES_F32 && c->dtype != 0)
+        rc = fail(c, LBMZ_EINVAL, "the narrow value formats need a float32 state");
+      c->vf = patch->values == LBMZ_VALUES_F16 ? VF_F16 : patch->values == LBMZ_VALUES_E4M3 ? VF_E4M3 : VF_F32;
+      c->key = KernelKey{c->dtype, p, c->wavelet, c->scheme, c->vf};
     }
   }
   if (rc == LBMZ_OK) {
@@ -688,6 +733,9 @@ int lbmz_stats(lbmz_ctx* c, lbmz_stats_t* out) {
     if (tab[2 * i + 1] & MASK_BIT) out->mask_records++;
     else out->list_records++;
   }
+  // narrow records depend on their subband count too; the pool is packed
+  // without gaps, so its used size is the sum of the record sizes
+  if (c->vf != VF_F32) rec = c->have_state ? (int64_t)c->used16 * 16 : 0;
   for (int f = 0; f < c->nfields && f < 16; ++f) {
     double s = 0.0;
     for (int q = 0; q < c->npatch; ++q) s += part[(size_t)q * c->nfields + f];
@@ -731,16 +779,44 @@ int lbmz_put_store(lbmz_ctx* c, const uint32_t* table_host, const void* pool_hos
   const size_t ne = (size_t)c->npatch * c->nfields;
   const uint8_t* pool = static_cast<const uint8_t*>(pool_host);
   const int64_t nc = ncoef(c), w = nwords(c);
+  // narrow records: record indices of the sample positions (never in a mask or list)
+  std::vector<uint64_t> sample_bits((size_t)w, 0ull);
+  if (c->vf != VF_F32) {
+    const int step = 1 << c->levels, p = c->p;
+    for (int y = 0; y < c->s; y += step)
+      for (int x = 0; x < c->s; x += step) {
+        int64_t k;
+        if (c->wavelet == W_HAAR || (x < p && y < p)) k = (int64_t)y * p + x;
+        else if (x == p && y < p) k = (int64_t)p * p + y;
+        else if (y == p && x < p) k = (int64_t)p * p + p + x;
+        else k = (int64_t)p * p + 2 * p;
+        sample_bits[(size_t)(k / 64)] |= 1ull << (k % 64);
+      }
+  }
+  const int64_t nbands = (int64_t)(c->levels + 1) * (c->levels + 1);
   for (size_t i = 0; i < ne; ++i) {
     const uint64_t off = (uint64_t)table_host[2 * i] * 16;
     const int64_t nnz = table_host[2 * i + 1] & ~MASK_BIT;
     const bool tagged_mask = (table_host[2 * i + 1] & MASK_BIT) != 0;
     bool mask = false;
     if (nnz > nc) return fail(c, LBMZ_EINVAL, "record %zu: nnz %lld > %lld", i, (long long)nnz, (long long)nc);
-    const int64_t rb = record_bytes(c, nnz, &mask);
+    int64_t rb, vb;
+    if (c->vf != VF_F32) {
+      if (off + 8 > pool_bytes) return fail(c, LBMZ_EINVAL, "record %zu overruns the pool", i);
+      uint64_t occ;
+      memcpy(&occ, pool + off, 8);
+      if ((occ & 1ull) || (nbands < 64 && (occ >> nbands) != 0))
+        return fail(c, LBMZ_EINVAL, "record %zu: bad subband mask", i);
+      const NarrowLayout l = narrow_layout(c, nnz, __builtin_popcountll(occ));
+      mask = l.mask;
+      rb = l.rb;
+      vb = l.vb;
+    } else {
+      rb = record_bytes(c, nnz, &mask);
+      vb = align_up(nnz * (int64_t)c->esize, 8);
+    }
     if (mask != tagged_mask) return fail(c, LBMZ_EINVAL, "record %zu: wrong encoding tag", i);
     if (off + (uint64_t)rb > pool_bytes) return fail(c, LBMZ_EINVAL, "record %zu overruns the pool", i);
-    const int64_t vb = align_up(nnz * (int64_t)c->esize, 8);
     if (mask) {
       int64_t cnt = 0;
       for (int64_t k = 0; k < w; ++k) {
@@ -748,6 +824,7 @@ int lbmz_put_store(lbmz_ctx* c, const uint32_t* table_host, const void* pool_hos
         memcpy(&word, pool + off + vb + 8 * k, 8);
         const int64_t valid = std::min<int64_t>(64, nc - 64 * k);
         if (valid < 64 && (word >> valid) != 0) return fail(c, LBMZ_EINVAL, "record %zu: bits past the tile", i);
+        if (word & sample_bits[(size_t)k]) return fail(c, LBMZ_EINVAL, "record %zu: sample in the detail mask", i);
         cnt += __builtin_popcountll(word);
       }
       if (cnt != nnz) return fail(c, LBMZ_EINVAL, "record %zu: mask count %lld != nnz", i, (long long)cnt);
@@ -756,7 +833,8 @@ int lbmz_put_store(lbmz_ctx* c, const uint32_t* table_host, const void* pool_hos
       for (int64_t k = 0; k < nnz; ++k) {
         uint16_t t;
         memcpy(&t, pool + off + vb + 2 * k, 2);
-        if ((int64_t)t <= prev || t >= nc) return fail(c, LBMZ_EINVAL, "record %zu: bad index list", i);
+        if ((int64_t)t <= prev || t >= nc || ((sample_bits[t / 64] >> (t % 64)) & 1ull))
+          return fail(c, LBMZ_EINVAL, "record %zu: bad index list", i);
         prev = t;
       }
     }

@@ -18,10 +18,11 @@ LIB_PATH = os.path.join(_HERE, "liblbmz.so")
 LBMZ_OK, LBMZ_EINVAL, LBMZ_ENOMEM, LBMZ_EDEVICE, LBMZ_EOVERFLOW, LBMZ_ENAN, LBMZ_ESTATE = 0, -1, -2, -3, -4, -5, -6
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "ENAN", -6: "ESTATE"}
 
-SCHEMES = {"fv_upwind": 0, "d2q9_bgk": 1}
+SCHEMES = {"fv_upwind": 0, "d2q9_bgk": 1, "euler_rusanov": 2}
 WAVELETS = {"haar": 0, "bl53": 1}
 RULES = {"capped": 0, "constant": 1, "accum": 2}
 DTYPES = {"f32": 0, "f64": 1}
+VALUES = {"f32": 0, "f16": 1, "e4m3": 2}
 NP_DTYPES = {"f32": np.float32, "f64": np.float64}
 MASK_BIT = 1 << 31
 
@@ -38,11 +39,11 @@ class Grid(ct.Structure):
 
 class Scheme(ct.Structure):
     _fields_ = [("kind", ct.c_int), ("dtype", ct.c_int), ("vel", ct.c_double * 3), ("cfl", ct.c_double),
-                ("tau", ct.c_double)]
+                ("tau", ct.c_double), ("gamma", ct.c_double)]
 
 
 class Patch(ct.Structure):
-    _fields_ = [("p", ct.c_int * 3), ("wavelet", ct.c_int), ("rule", ct.c_int)]
+    _fields_ = [("p", ct.c_int * 3), ("wavelet", ct.c_int), ("rule", ct.c_int), ("values", ct.c_int)]
 
 
 class Stats(ct.Structure):
@@ -119,21 +120,23 @@ class Context:
     def __init__(self, n: int, scheme: str = "d2q9_bgk", dtype: str = "f32", p: int = 64,
                  wavelet: str = "bl53", levels: int = 5, eps: float = 1e-4, rule: str = "capped",
                  vel=(1.0, 0.5), cfl: float = 0.5, tau: float = 0.6, reference: bool = False,
-                 stream=None, torch_allocator: bool = False, pool_capacity: int | None = None):
+                 stream=None, torch_allocator: bool = False, pool_capacity: int | None = None,
+                 values: str = "f32", gamma: float = 1.4):
         self._lib = library()
         self.n, self.scheme, self.dtype, self.p = n, scheme, dtype, p
+        self.values = values
         self.wavelet, self.levels, self.eps, self.rule = wavelet, levels, eps, rule
         self.reference = reference
         self.np_dtype = NP_DTYPES[dtype]
-        self.nfields = 9 if scheme == "d2q9_bgk" else 1
+        self.nfields = {"d2q9_bgk": 9, "euler_rusanov": 4}.get(scheme, 1)
         self.s = (p + 1 if wavelet == "bl53" else p) if not reference else n
         g = Grid(2, (ct.c_int64 * 3)(n, n, 1), 1, 1.0 / n)
-        sc = Scheme(SCHEMES[scheme], DTYPES[dtype], (ct.c_double * 3)(vel[0], vel[1], 0.0), cfl, tau)
+        sc = Scheme(SCHEMES[scheme], DTYPES[dtype], (ct.c_double * 3)(vel[0], vel[1], 0.0), cfl, tau, gamma)
         h = ct.c_void_p()
         if reference:
             rc = self._lib.lbmz_create_reference(ct.byref(g), ct.byref(sc), ct.byref(h))
         else:
-            pt = Patch((ct.c_int * 3)(p, p, 1), WAVELETS[wavelet], RULES[rule])
+            pt = Patch((ct.c_int * 3)(p, p, 1), WAVELETS[wavelet], RULES[rule], VALUES[values])
             rc = self._lib.lbmz_create(ct.byref(g), ct.byref(sc), ct.byref(pt), levels, eps, ct.byref(h))
         if rc != LBMZ_OK:
             raise LbmzError(rc, "create failed (invalid geometry, levels, scheme or no kernel for the key)")
@@ -270,12 +273,67 @@ def record_order(s: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.int64)
 
 
-def decode_records(table: np.ndarray, pool: bytes, s: int, dtype) -> np.ndarray:
+def _e4m3_values(codes: np.ndarray) -> np.ndarray:
+    c = codes.astype(np.int64)
+    e = (c >> 3) & 15
+    m = (c & 7).astype(np.float64)
+    mag = np.where(e == 0, m * 2.0 ** -9, (1.0 + m / 8.0) * np.exp2(e - 7.0))
+    return np.where(c & 0x80, -mag, mag).astype(np.float32)
+
+
+def _decode_narrow(table, pool, s, values, levels):
+    npatch, nf = table.shape[:2]
+    nc = s * s
+    w = (nc + 63) // 64
+    order = record_order(s)
+    step = 1 << levels
+    sc = (s - 1) // step + 1
+    ns = sc * sc
+    cls = np.array([0 if i % step == 0 else (i & -i).bit_length() for i in range(s)])
+    band = (cls[:, None] * (levels + 1) + cls[None, :]).reshape(-1)[order]
+    by = 2 if values == "f16" else 1
+    buf = np.frombuffer(pool, dtype=np.uint8)
+    out = np.zeros((npatch, nf, s, s), dtype=np.float32)
+    for q in range(npatch):
+        for f in range(nf):
+            off = int(table[q, f, 0]) * 16
+            word = int(table[q, f, 1])
+            ndet = word & (MASK_BIT - 1)
+            occ = int(buf[off:off + 8].view("<u8")[0])
+            bands = [b for b in range(64) if (occ >> b) & 1]
+            scale = dict(zip(bands, buf[off + 8:off + 8 + 4 * len(bands)].view("<f4")))
+            hb = (8 + 4 * len(bands) + 7) // 8 * 8
+            sb = hb + (4 * ns + 7) // 8 * 8
+            vb = sb + (by * ndet + 7) // 8 * 8
+            samp = buf[off + hb:off + hb + 4 * ns].view("<f4").reshape(sc, sc)
+            out[q, f, ::step, ::step] = samp
+            if ndet == 0:
+                continue
+            raw = buf[off + sb:off + sb + by * ndet]
+            vals = raw.view("<f2").astype(np.float32) if values == "f16" else _e4m3_values(raw)
+            if word & MASK_BIT:
+                bits = np.unpackbits(buf[off + vb:off + vb + 8 * w], bitorder="little")[:nc].astype(bool)
+                ks = np.flatnonzero(bits)
+            else:
+                ks = buf[off + vb:off + vb + 2 * ndet].view("<u2").astype(np.int64)
+            sc_of = np.array([scale[int(b)] for b in band[ks]], dtype=np.float32)
+            flat = out[q, f].reshape(-1)
+            flat[order[ks]] = vals * sc_of
+    return out
+
+
+def decode_records(table: np.ndarray, pool: bytes, s: int, dtype, values: str = "f32",
+                   levels: int | None = None) -> np.ndarray:
     """Coefficient tiles ``[npatch, nfields, s, s]`` from a store (host-side reader).
 
-    Reads the record layout of include/lbmz.h; used to inspect what the
-    library wrote.
+    Reads the record layouts of include/lbmz.h; used to inspect what the
+    library wrote.  The narrow value formats need the level count and give
+    float32 tiles as read back (details times their subband scale).
     """
+    if values != "f32":
+        if levels is None:
+            raise ValueError("narrow records need the level count")
+        return _decode_narrow(table, pool, s, values, levels)
     dtype = np.dtype(dtype)
     npatch, nf = table.shape[:2]
     nc = s * s

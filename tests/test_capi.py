@@ -33,8 +33,8 @@ def test_struct_sizes_match_header():
     from paper_2302_09883_amd.lbmz import Grid, Patch, Scheme, Stats
     # sizes of the C structs under the x86-64 SysV ABI
     assert ct.sizeof(Grid) == 4 + 4 + 24 + 4 + 4 + 8
-    assert ct.sizeof(Scheme) == 4 + 4 + 24 + 8 + 8
-    assert ct.sizeof(Patch) == 12 + 4 + 4
+    assert ct.sizeof(Scheme) == 4 + 4 + 24 + 8 + 8 + 8
+    assert ct.sizeof(Patch) == 12 + 4 + 4 + 4
     assert ct.sizeof(Stats) == 8 * 5 + 8 + 4 + 4 + 16 * 8 + 8 * 3 + 8
 
 

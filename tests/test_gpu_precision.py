@@ -1,0 +1,194 @@
+"""GPU parity of the narrow value formats (float32 samples, binary16 / E4M3 details).
+
+* Compaction fed the same coefficients: every record byte-identical to the
+  oracle's (threshold decisions, subband scales, codes, samples, encoding).
+* Expansion: a store written by the oracle reads back to the oracle's tiles.
+* One step from a common state: the stored tiles agree up to the rounding of
+  the float32 arithmetic carried through one quantisation.
+* Multi-step runs: mass and momentum conserved to float32 round-off, the
+  store smaller than the float32 format's, fields close to the oracle's.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lbmz_oracle as O
+from oracle import lbmz_precision as Q
+from synth import random_coefficient_tiles, shear_layer_macroscopic, fv_gaussians_and_step
+
+from gpu_helpers import make_ctx, require_gpu, torch  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+GEOMS = [
+    (128, "d2q9_bgk", 64, "bl53", 5),
+    (64, "d2q9_bgk", 32, "bl53", 3),
+    (128, "d2q9_bgk", 64, "haar", 4),
+    (128, "fv_upwind", 64, "bl53", 5),
+    (64, "fv_upwind", 32, "haar", 5),
+]
+
+
+def _say(*args):
+    print("[case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _record(table, pool, q, f, g, levels, fmt):
+    """Bytes of one narrow record, sized by the oracle's layout rule."""
+    off = int(table[q, f, 0]) * 16
+    word = int(table[q, f, 1])
+    ndet = word & (O.MASK_BIT - 1)
+    occ = int(np.frombuffer(pool, dtype="<u8", count=1, offset=off)[0])
+    nsamp = len(Q.sample_positions(g.s, levels)[0])
+    rb = Q.record_layout_q(ndet, bin(occ).count("1"), g.s * g.s, nsamp, fmt)[4]
+    return pool[off:off + rb]
+
+
+def _twin(n, scheme, p, wavelet, levels, eps, fmt, rule="capped"):
+    g = O.Geometry(n, p, wavelet, levels)
+    return O.CompressedRun(g, O.Scheme(scheme, vel=(1.0, 0.5), cfl=0.5, tau=0.6), eps, rule, np.float32,
+                           values=fmt)
+
+
+def _state(n, scheme, seed=0):
+    if scheme == "d2q9_bgk":
+        rho, ux, uy = shear_layer_macroscopic(n, seed=seed, u0=0.05, kappa=20.0)
+        return O.d2q9_equilibrium(rho, ux, uy).astype(np.float32)
+    return fv_gaussians_and_step(n, seed=seed).astype(np.float32)[None]
+
+
+def _set_state(ctx, state):
+    if ctx.scheme == "d2q9_bgk":
+        for f in range(9):
+            ctx.set_field(f, state[f])
+    else:
+        ctx.set_field(0, state[0])
+
+
+@pytest.mark.parametrize("fmt", Q.FORMATS)
+@pytest.mark.parametrize("geom", GEOMS)
+@pytest.mark.parametrize("eps,zero_frac", [(0.0, 0.3), (1e-3, 0.0), (1e-2, 0.99)])
+def test_narrow_compaction_byte_exact(fmt, geom, eps, zero_frac):
+    n, scheme, p, wavelet, levels = geom
+    _say("narrow compaction", fmt, geom, eps)
+    ctx = make_ctx(n, scheme, "f32", p, wavelet, levels, eps, values=fmt)
+    twin = _twin(n, scheme, p, wavelet, levels, eps, fmt)
+    g = twin.g
+    tiles = random_coefficient_tiles((g.npatch, ctx.nfields, g.s, g.s), seed=(7 * n + p + 3 * len(fmt)) % 997,
+                                     zero_frac=zero_frac, scale_spread=5.0)
+    tiles[0, 0] = 0                       # an empty record, and a sparse one
+    tiles[0, 0, 0, :3] = 1.25
+    ctx.set_coefficients(tiles)
+    kept = O.hard_threshold(tiles, twin.thr)
+    table, pool = ctx.store()
+    for q in range(g.npatch):
+        for f in range(ctx.nfields):
+            rec, ndet, is_mask = Q.encode_record_q(kept[q, f], levels, fmt)
+            assert int(table[q, f, 1]) == ndet | (O.MASK_BIT if is_mask else 0), (q, f)
+            assert _record(table, pool, q, f, g, levels, fmt) == rec, (q, f)
+    spans = sorted((int(table[q, f, 0]) * 16, len(_record(table, pool, q, f, g, levels, fmt)))
+                   for q in range(g.npatch) for f in range(ctx.nfields))
+    pos = 0
+    for off, ln in spans:
+        assert off == pos
+        pos += ln
+    assert pos == len(pool)
+    st = ctx.stats()
+    assert st["store_bytes"] == len(pool) + table.size * 4
+
+
+@pytest.mark.parametrize("fmt", Q.FORMATS)
+@pytest.mark.parametrize("geom", GEOMS)
+def test_narrow_store_reads_back(fmt, geom):
+    n, scheme, p, wavelet, levels = geom
+    _say("narrow restore", fmt, geom)
+    ctx = make_ctx(n, scheme, "f32", p, wavelet, levels, 1e-3, values=fmt)
+    twin = _twin(n, scheme, p, wavelet, levels, 1e-3, fmt)
+    twin.set_grid(_state(n, scheme))
+    table, pool = twin.store()
+    ctx.put_store(table, pool)
+    got = ctx.fields()
+    want = twin.grid()
+    assert np.max(np.abs(got - want)) <= 2e-6 * np.max(np.abs(want))
+    t2, p2 = ctx.store()
+    assert np.array_equal(t2, table) and p2 == pool
+    from paper_2302_09883_amd import decode_records
+    tiles = decode_records(table, pool, twin.g.s, np.float32, values=fmt, levels=levels)
+    assert np.array_equal(tiles.view(np.uint32), twin.coef.view(np.uint32))
+
+
+@pytest.mark.parametrize("fmt", Q.FORMATS)
+@pytest.mark.parametrize("geom", GEOMS)
+@pytest.mark.parametrize("eps", [1e-4, 1e-3])
+def test_narrow_one_step_from_common_state(fmt, geom, eps):
+    n, scheme, p, wavelet, levels = geom
+    _say("narrow one-step", fmt, geom, eps)
+    from paper_2302_09883_amd import decode_records
+    ctx = make_ctx(n, scheme, "f32", p, wavelet, levels, eps, values=fmt)
+    twin = _twin(n, scheme, p, wavelet, levels, eps, fmt)
+    twin.set_grid(_state(n, scheme, seed=3))
+    twin.step(2)
+    table, pool = twin.store()
+    ctx.put_store(table, pool)
+    ctx.step(1)
+    twin.step(1)
+    t2, p2 = ctx.store()
+    got = decode_records(t2, p2, twin.g.s, np.float32, values=fmt, levels=levels)
+    want = twin.coef
+    scale = float(np.max(np.abs(twin.grid())))
+    u = np.finfo(np.float32).eps
+    # a keep / drop flip only for a coefficient at its threshold
+    kg = (t2[..., 1] & (O.MASK_BIT - 1)).astype(np.int64)
+    kw = twin.nnz()
+    assert np.all(np.abs(kg - kw) <= 2 + kw // 100)
+    # codes: one step of the narrow format's rounding at the subband scale
+    rel = 2.0 ** -10 if fmt == "f16" else 2.0 ** -3
+    d = np.abs(got.astype(np.float64) - want)
+    bound = rel * np.maximum(np.abs(want), np.abs(got)) + 256 * u * scale + 2 * twin.thr.max()
+    assert np.all(d <= bound)
+    # the samples are stored exactly: compare them to round-off
+    sb = Q.subband_table(twin.g.s, levels) == 0
+    assert np.max(np.abs(got[..., sb] - want[..., sb])) <= 256 * u * scale
+
+
+@pytest.mark.parametrize("fmt", Q.FORMATS)
+def test_narrow_run_conserves_and_shrinks(fmt):
+    n, p, levels, eps = 256, 64, 5, 0.0
+    _say("narrow run", fmt)
+    rho, ux, uy = shear_layer_macroscopic(n, seed=1)
+    macro = [a.astype(np.float32) for a in (rho, ux, uy)]
+    runs = {}
+    for v in ("f32", fmt):
+        ctx = make_ctx(n, "d2q9_bgk", "f32", p, "bl53", levels, eps, values=v)
+        ctx.set_macroscopic(*macro)
+        t0 = np.array(ctx.stats()["totals"])
+        ctx.step(40)
+        st = ctx.stats()
+        t1 = np.array(st["totals"])
+        # mass and momentum of the stored state conserved to float32 round-off
+        c = O.D2Q9_C
+        assert abs(t1.sum() - t0.sum()) <= 2e-6 * abs(t0.sum())
+        for ax in (0, 1):
+            assert abs((c[:, ax] * t1).sum() - (c[:, ax] * t0).sum()) <= 2e-6 * abs(t0.sum())
+        runs[v] = (st["store_bytes"], ctx.fields())
+    assert runs[fmt][0] < runs["f32"][0]
+    # the quantised run stays close to the float32 one
+    a, b = runs["f32"][1], runs[fmt][1]
+    rel = np.linalg.norm(a - b) / np.linalg.norm(a)
+    print("[case] narrow run rel_l2 vs float32 records", fmt, rel, "store bytes", runs[fmt][0], runs["f32"][0])
+    assert rel <= (1e-4 if fmt == "f16" else 2e-2), rel
+
+
+def test_narrow_formats_need_float32():
+    from paper_2302_09883_amd import LbmzError
+    with pytest.raises(LbmzError):
+        make_ctx(64, "fv_upwind", "f64", 32, "haar", 3, 1e-3, values="f16")
+    with pytest.raises(LbmzError):
+        make_ctx(64, "fv_upwind", "f32", 16, "haar", 3, 1e-3, values="e4m3")   # no kernel for p = 16
