@@ -224,6 +224,56 @@ int lbmz_stats(lbmz_ctx* ctx, lbmz_stats_t* out);
  * Record placement in the pool is not canonical (any non-overlapping layout
  * is valid); the records themselves are. */
 
+/* ---- per-patch thresholds and the learned predictor's inputs ------------ */
+
+/* Per-patch threshold constants: eps[q] replaces the context's eps for patch
+ * q (patch index px + (n/p) py) in every following step and set-up call;
+ * count = npatch (host values must be finite and >= 0; device values are the
+ * caller's responsibility), or count = 0 to return to the single eps.  The
+ * threshold rule and levels stay those of the context (Section 2.2 gives one
+ * constant per run; a constant per patch is the learned part's control). */
+int lbmz_set_patch_eps(lbmz_ctx* ctx, const double* eps, size_t count, int on_device);
+
+/* With on != 0, every step also writes each patch's network input: the
+ * stored coefficients of every field at the owned positions (8 i, 8 j),
+ * i, j < 8, as float [npatch][nfields][8][8] (y major).  64 x 64 patches
+ * only (LBMZ_EINVAL otherwise). */
+int lbmz_enable_features(lbmz_ctx* ctx, int on);
+
+/* Copy the inputs written by the last completed lbmz_step; LBMZ_ESTATE when
+ * they are not enabled or no step has completed since. */
+int lbmz_get_features(lbmz_ctx* ctx, float* dst, size_t bytes, int dst_on_device);
+
+/* ---- the learned threshold predictor ---------------------------------------
+ * A small convolutional network (bfloat16 weights, float32 accumulation) that
+ * maps a patch's network input (lbmz_get_features) to K predicted log10
+ * squared errors, one per candidate threshold:
+ *   asinh(x / 1e-4) [9][8][8] -> conv 3x3 9->32, ReLU -> conv 3x3 32->32, ReLU
+ *   -> conv 3x3 stride 2 32->32, ReLU -> mean over 4 x 4 -> linear 32->K.
+ * Parameters, float32, in this order: w1[32][9][3][3], b1[32],
+ * w2[32][32][3][3], b2[32], w3[32][32][3][3], b3[32], wh[K][32], bh[K]
+ * (21120 + 33 K values).  The float32 master copy is what set/get exchange;
+ * every pass uses its round-to-nearest-even bfloat16 copy.  Loss of a batch:
+ * the mean of its B x K squared differences to the targets; training is Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on the master copy.  x: [B][9][8][8],
+ * targets and outputs: [B][K], float32, host or device (on_device). */
+typedef struct lbmz_net lbmz_net;
+int lbmz_net_create(int k, lbmz_net** out);          /* 1 <= k <= 16; parameters start at 0 */
+int lbmz_net_param_count(const lbmz_net* net);
+int lbmz_net_set_stream(lbmz_net* net, void* hip_stream);
+int lbmz_net_set_params(lbmz_net* net, const float* params, size_t count);   /* host; resets Adam */
+int lbmz_net_get_params(lbmz_net* net, float* params, size_t count);         /* host */
+int lbmz_net_forward(lbmz_net* net, const float* x, int batch, float* y, int on_device);
+/* Gradients of the batch loss with respect to the parameters (host buffer of
+ * count parameters) and the loss; for checks against a reference. */
+int lbmz_net_gradients(lbmz_net* net, const float* x, const float* t, int batch, float* grad_host, float* loss,
+                       int on_device);
+/* One Adam step on the batch; *loss (may be null) is the loss before the step. */
+int lbmz_net_train_step(lbmz_net* net, const float* x, const float* t, int batch, float lr, float* loss,
+                        int on_device);
+const char* lbmz_net_last_error(const lbmz_net* net);
+void lbmz_net_destroy(lbmz_net* net);
+
 /* Sizes of the current store: pool bytes in use and offset-table entries. */
 int lbmz_store_size(lbmz_ctx* ctx, int64_t* pool_bytes, int64_t* table_entries);
 

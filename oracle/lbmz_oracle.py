@@ -703,6 +703,14 @@ class CompressedRun:
         self.coef = self.compress_tiles(extract_tiles(np.asarray(grid, dtype=self.dtype), self.g))
         self.steps = 0
 
+    def set_patch_eps(self, eps=None):
+        """One threshold constant per patch (the learned control), or None for the single eps."""
+        if eps is None:
+            self.thr = threshold_table(self.g.s, self.g.levels, self.eps, self.rule, self.dtype)
+        else:
+            self.thr = np.stack([threshold_table(self.g.s, self.g.levels, float(e), self.rule, self.dtype)
+                                 for e in eps])[:, None]
+
     def set_coefficients(self, coef: np.ndarray, threshold: bool = True):
         c = np.asarray(coef, dtype=self.dtype)
         self.coef = self._store_form(hard_threshold(c, self.thr) if threshold else c.copy())

@@ -6,6 +6,7 @@ package only exposes its C ABI (``include/lbmz.h``) to Python.
 from .lbmz import (  # noqa: F401
     Context,
     LbmzError,
+    Net,
     decode_records,
     library,
     LIB_PATH,

@@ -27,6 +27,7 @@ SOURCES = [
     "lbmz_inst_f32_fv_q.hip",
     "lbmz_inst_f32_lbm_q.hip",
     "lbmz_inst_f32_euler.hip",
+    "lbmz_net.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -40,6 +40,8 @@ struct PatchArgs {
   int levels;        // wavelet levels per dimension
   int rule;          // Rule
   double eps;        // threshold constant
+  const double* eps_patch;       // per-patch threshold constants [npatch], or null for eps
+  float* features;               // per-patch stride-8 coefficients [npatch][M][8][8], or null
   // scheme
   double dt_over_h;  // FV
   double cp[4];      // FV: max(a.N^k, 0)

@@ -408,6 +408,24 @@ __device__ __forceinline__ void threshold_column(T* v, int x, int L, T eps, int 
   }
 }
 
+// Threshold constant of patch q: the per-patch value when one is set.
+__device__ __forceinline__ double patch_eps(const PatchArgs& a, int q) {
+  return a.eps_patch ? a.eps_patch[q] : a.eps;
+}
+
+// Network input of patch q: the stored coefficients of the owned positions
+// of stride 8 (8 x 8 per field), from the column of lane x (x = 8 i).
+template <class C, class T>
+__device__ __forceinline__ void export_features(const PatchArgs& a, int q, int f, int x, const T* v) {
+  if constexpr (C::P == 64) {
+    if (a.features && (x & 7) == 0 && x < C::P) {
+      float* dst = a.features + ((size_t)q * C::M + f) * 64 + (x >> 3);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) dst[8 * i] = (float)v[8 * i];
+    }
+  }
+}
+
 // S9 partial of one column of coefficients: trapezoid weights of the coarse
 // samples (1/2 on the tile ends for BL5/3), FP64, ascending y.  The level
 // count is uniform, so the branch on it is scalar and only the samples are
@@ -1018,7 +1036,7 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm
   if (act) {
     load_col<C>(v, sm.tile, field_base<C>(f), x);
     if constexpr (FWD) LF::fwd(v, L);
-    threshold_column<C, T>(v, x, L, T(a.eps), a.rule);
+    threshold_column<C, T>(v, x, L, T(patch_eps(a, q)), a.rule);
     if constexpr (!FWD) {
       // Given coefficients: a scaled sum of magnitudes stays finite for any
       // finite column and turns into Inf / NaN with any non-finite element.
@@ -1193,6 +1211,7 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm
   }
   totals_finish<C, T, FWD>(a, a.partials_out + (size_t)q * C::M, L, sm);
   LBMZ_MARK(11);
+  if (wave < C::M && act) export_features<C, T>(a, q, f, x, v);
 
   // S8, column half: inverse of the thresholded column, back to LDS.
   if (act) {

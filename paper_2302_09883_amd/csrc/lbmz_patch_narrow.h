@@ -139,7 +139,7 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
   if (act) {
     load_col<C>(v, sm.tile, field_base<C>(f), x);
     if constexpr (FWD) LF::fwd(v, L);
-    threshold_column<C, T>(v, x, L, T(a.eps), a.rule);
+    threshold_column<C, T>(v, x, L, T(patch_eps(a, q)), a.rule);
     if constexpr (!FWD) {
 #pragma unroll
       for (int y = 0; y < C::S; ++y) mag = fma(fabs(v[y]), T(0x1p-64), mag);
@@ -397,6 +397,7 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
     zero_bytes(rec, mend, sm.rb[g]);
   }
   totals_finish<C, T, FWD>(a, a.partials_out + (size_t)q * C::M, L, sm);
+  if (wave < C::M && act) export_features<C, T>(a, q, f, x, v);
 
   // S8, column half: inverse of the stored column, back to LDS.
   if (act) {

@@ -69,6 +69,9 @@ struct lbmz_ctx {
   size_t esize = 4;
   int n = 0, p = 0, npx = 0, npatch = 0, s = 0, levels = 0, wavelet = 0, rule = 0, scheme = 0;
   int vf = VF_F32;   // ValueFormat of the records
+  double* eps_patch = nullptr;   // per-patch thresholds (device), or null
+  float* features = nullptr;     // per-patch network inputs of the last step (device), or null
+  bool features_valid = false;
   int nfields = 1, nslot = 1;
   double eps = 0.0;
   KernelKey key{};
@@ -272,6 +275,8 @@ PatchArgs args_for(lbmz_ctx* c, int in, int out, unsigned epoch) {
   a.cap16 = (unsigned long long)(c->cap_bytes / 16);
   a.ctrl = c->ctrl;
   a.epoch = epoch;
+  a.eps_patch = c->eps_patch;
+  a.features = c->features;
   return a;
 }
 
@@ -635,6 +640,7 @@ int lbmz_step(lbmz_ctx* c, int n) {
     remaining -= kbad;
     if (h.abort & ABORT_NONFINITE) {
       reset_ctrl(c);
+      c->features_valid = false;
       return fail(c, LBMZ_ENAN, "non-finite coefficient at step %lld; state kept at the previous step",
                   (long long)c->steps + 1);
     }
@@ -649,6 +655,7 @@ int lbmz_step(lbmz_ctx* c, int n) {
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
   c->ms_last = ms;
+  c->features_valid = c->features != nullptr && n > 0;
   return LBMZ_OK;
 }
 
@@ -892,6 +899,62 @@ int lbmz_set_coefficients(lbmz_ctx* c, const void* coef, size_t bytes, int on_de
   return rc;
 }
 
+int lbmz_set_patch_eps(lbmz_ctx* c, const double* eps, size_t count, int on_device) {
+  if (!c) return LBMZ_EINVAL;
+  if (c->reference) return fail(c, LBMZ_ESTATE, "a reference context has no threshold");
+  if (count == 0) {
+    if (c->eps_patch) {
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      dfree(c, c->eps_patch);
+      c->eps_patch = nullptr;
+    }
+    return LBMZ_OK;
+  }
+  if (!eps) return LBMZ_EINVAL;
+  if (count != (size_t)c->npatch)
+    return fail(c, LBMZ_EINVAL, "expected %d per-patch thresholds, got %zu", c->npatch, count);
+  if (!on_device) {
+    for (size_t q = 0; q < count; ++q)
+      if (!(eps[q] >= 0.0) || !std::isfinite(eps[q]))
+        return fail(c, LBMZ_EINVAL, "threshold of patch %zu must be finite and >= 0", q);
+  }
+  if (!c->eps_patch) {
+    c->eps_patch = static_cast<double*>(dalloc(c, count * sizeof(double)));
+    if (!c->eps_patch) return fail(c, LBMZ_ENOMEM, "per-patch threshold allocation failed");
+  }
+  return copy_in(c, c->eps_patch, eps, count * sizeof(double), on_device);
+}
+
+int lbmz_enable_features(lbmz_ctx* c, int on) {
+  if (!c) return LBMZ_EINVAL;
+  if (c->reference) return fail(c, LBMZ_ESTATE, "a reference context has no coefficients");
+  if (on) {
+    if (c->p != 64) return fail(c, LBMZ_EINVAL, "patch features need 64 x 64 patches");
+    if (!c->features) {
+      c->features = static_cast<float*>(dalloc(c, (size_t)c->npatch * c->nfields * 64 * sizeof(float)));
+      if (!c->features) return fail(c, LBMZ_ENOMEM, "feature buffer allocation failed");
+    }
+  } else if (c->features) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(c, c->features);
+    c->features = nullptr;
+  }
+  c->features_valid = false;
+  return LBMZ_OK;
+}
+
+int lbmz_get_features(lbmz_ctx* c, float* dst, size_t bytes, int dst_on_device) {
+  if (!c || !dst) return LBMZ_EINVAL;
+  if (!c->features) return fail(c, LBMZ_ESTATE, "features are not enabled");
+  if (!c->features_valid) return fail(c, LBMZ_ESTATE, "no step has written the features yet");
+  const size_t want = (size_t)c->npatch * c->nfields * 64 * sizeof(float);
+  if (bytes != want) return fail(c, LBMZ_EINVAL, "expected %zu bytes of features, got %zu", want, bytes);
+  HIPCHK(c, hipMemcpyAsync(dst, c->features, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->stream));
+  if (!dst_on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBMZ_OK;
+}
+
 const char* lbmz_last_error(const lbmz_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 void lbmz_destroy(lbmz_ctx* c) {
@@ -905,6 +968,8 @@ void lbmz_destroy(lbmz_ctx* c) {
     dfree(c, c->dense[b]);
   }
   dfree(c, c->ctrl);
+  dfree(c, c->eps_patch);
+  dfree(c, c->features);
   if (c->ctrl_host) (void)hipHostFree(c->ctrl_host);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);

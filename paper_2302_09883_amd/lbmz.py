@@ -86,7 +86,20 @@ def library() -> ct.CDLL:
         "lbmz_get_store": ([vp, vp, vp, ct.c_size_t], ct.c_int),
         "lbmz_put_store": ([vp, vp, vp, ct.c_size_t], ct.c_int),
         "lbmz_set_coefficients": ([vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
+        "lbmz_set_patch_eps": ([vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
+        "lbmz_enable_features": ([vp, ct.c_int], ct.c_int),
+        "lbmz_get_features": ([vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
         "lbmz_last_error": ([vp], ct.c_char_p),
+        "lbmz_net_create": ([ct.c_int, P(vp)], ct.c_int),
+        "lbmz_net_param_count": ([vp], ct.c_int),
+        "lbmz_net_set_stream": ([vp, vp], ct.c_int),
+        "lbmz_net_set_params": ([vp, vp, ct.c_size_t], ct.c_int),
+        "lbmz_net_get_params": ([vp, vp, ct.c_size_t], ct.c_int),
+        "lbmz_net_forward": ([vp, vp, ct.c_int, vp, ct.c_int], ct.c_int),
+        "lbmz_net_gradients": ([vp, vp, vp, ct.c_int, vp, P(ct.c_float), ct.c_int], ct.c_int),
+        "lbmz_net_train_step": ([vp, vp, vp, ct.c_int, ct.c_float, P(ct.c_float), ct.c_int], ct.c_int),
+        "lbmz_net_last_error": ([vp], ct.c_char_p),
+        "lbmz_net_destroy": ([vp], None),
         "lbmz_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
@@ -211,6 +224,27 @@ class Context:
         self._check(self._lib.lbmz_set_coefficients(self._h, ptr, nb, dev))
         del keep
 
+    def set_patch_eps(self, eps=None):
+        """Per-patch thresholds ``[npatch]`` (float64, host or device), or None for the single eps."""
+        if eps is None:
+            self._check(self._lib.lbmz_set_patch_eps(self._h, None, 0, 0))
+            return
+        ptr, nb, dev, keep = _buffer(eps, np.float64)
+        self._check(self._lib.lbmz_set_patch_eps(self._h, ptr, nb // 8, dev))
+        del keep
+
+    def enable_features(self, on: bool = True):
+        self._check(self._lib.lbmz_enable_features(self._h, int(bool(on))))
+
+    def features(self, out=None):
+        """Network inputs of the last step, ``float32 [npatch, nfields, 8, 8]`` (host unless ``out`` is a device tensor)."""
+        npatch = (self.n // self.p) ** 2
+        if out is None:
+            out = np.empty((npatch, self.nfields, 8, 8), dtype=np.float32)
+        ptr, nb, dev, keep = _buffer(out, np.float32)
+        self._check(self._lib.lbmz_get_features(self._h, ptr, nb, dev))
+        return out
+
     def step(self, n: int = 1):
         self._check(self._lib.lbmz_step(self._h, int(n)))
 
@@ -251,6 +285,76 @@ class Context:
         buf = np.frombuffer(pool, dtype=np.uint8)
         self._check(self._lib.lbmz_put_store(self._h, ct.c_void_p(t.ctypes.data),
                                              ct.c_void_p(buf.ctypes.data), buf.nbytes))
+
+
+class Net:
+    """The learned threshold predictor of include/lbmz.h (bfloat16 weights, float32 accumulation)."""
+
+    def __init__(self, k: int, stream=None):
+        self._lib = library()
+        h = ct.c_void_p()
+        rc = self._lib.lbmz_net_create(int(k), ct.byref(h))
+        if rc != LBMZ_OK:
+            raise LbmzError(rc, "network creation failed")
+        self._h = h
+        self.k = int(k)
+        self.nparams = int(self._lib.lbmz_net_param_count(h))
+        if stream is None:
+            stream = _current_stream()
+        self._check(self._lib.lbmz_net_set_stream(h, ct.c_void_p(stream)))
+
+    def _check(self, rc):
+        if rc != LBMZ_OK:
+            msg = self._lib.lbmz_net_last_error(self._h)
+            raise LbmzError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbmz_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # noqa: BLE001
+            pass
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self._lib.lbmz_net_set_params(self._h, ct.c_void_p(a.ctypes.data), a.size))
+
+    def params(self) -> np.ndarray:
+        a = np.empty(self.nparams, dtype=np.float32)
+        self._check(self._lib.lbmz_net_get_params(self._h, ct.c_void_p(a.ctypes.data), a.size))
+        return a
+
+    def forward(self, x, out=None):
+        ptr, nb, dev, keep = _buffer(x, np.float32)
+        batch = nb // (9 * 64 * 4)
+        if out is None:
+            out = np.empty((batch, self.k), dtype=np.float32)
+        optr, _, odev, okeep = _buffer(out, np.float32)
+        if odev != dev:
+            raise ValueError("inputs and outputs must live on the same side")
+        self._check(self._lib.lbmz_net_forward(self._h, ptr, batch, optr, dev))
+        return out
+
+    def gradients(self, x, t):
+        xa = np.ascontiguousarray(x, dtype=np.float32)
+        ta = np.ascontiguousarray(t, dtype=np.float32)
+        g = np.empty(self.nparams, dtype=np.float32)
+        loss = ct.c_float()
+        self._check(self._lib.lbmz_net_gradients(self._h, ct.c_void_p(xa.ctypes.data), ct.c_void_p(ta.ctypes.data),
+                                                 xa.shape[0], ct.c_void_p(g.ctypes.data), ct.byref(loss), 0))
+        return g, float(loss.value)
+
+    def train_step(self, x, t, lr: float) -> float:
+        xp, xb, xdev, xk = _buffer(x, np.float32)
+        tp, tb, tdev, tk = _buffer(t, np.float32)
+        loss = ct.c_float()
+        self._check(self._lib.lbmz_net_train_step(self._h, xp, tp, xb // (9 * 64 * 4), ct.c_float(lr),
+                                                  ct.byref(loss), xdev))
+        return float(loss.value)
 
 
 def _current_stream():

@@ -17,6 +17,7 @@ from .fields import (
     random_coefficient_tiles,
     transport_gaussian,
     riemann_four_quadrants,
+    shear_with_vortices,
 )
 
 __all__ = [
@@ -28,4 +29,5 @@ __all__ = [
     "random_coefficient_tiles",
     "transport_gaussian",
     "riemann_four_quadrants",
+    "shear_with_vortices",
 ]

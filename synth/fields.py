@@ -187,3 +187,36 @@ def riemann_four_quadrants(n: int = 4096, seed: int = 0, gamma: float = 1.4,
     w[0] = rho
     w[3] = p / (gamma - 1.0)
     return w, [(float(rho_q[k]), float(p_q[k])) for k in range(4)]
+
+
+def shear_with_vortices(n: int = 1024, seed: int = 0, u0: float = 0.05, kappa: float = 80.0,
+                        delta: float = 0.05, n_vortices: int = 12, radius_range=(0.02, 0.06),
+                        strength_range=(0.5, 1.0)):
+    """Double shear layer plus seeded Gaussian vortices, as ``(rho, ux, uy)``.
+
+    The shear layer is :func:`shear_layer_macroscopic` with the same seed.
+    Then, from ``default_rng(seed + 7919)``: vortex centres ``(n_vortices, 2)``
+    uniform in the unit square, core radii uniform in ``radius_range``, peak
+    speeds uniform in ``strength_range`` times ``u0``, signs from a fair coin.
+    Vortex ``k`` adds the velocity ``s_k r_k / r * exp(1/2 - r^2 / (2 r_k^2))
+    * (r / r_k)`` in the azimuthal direction (a Gaussian vortex whose speed
+    peaks at ``r = r_k`` with value ``s_k``), with the periodic minimum-image
+    offset ``r`` from its centre.  Density stays 1.
+    """
+    rho, ux, uy = shear_layer_macroscopic(n, seed=seed, u0=u0, kappa=kappa, delta=delta)
+    rng = np.random.default_rng(seed + 7919)
+    centres = rng.uniform(0.0, 1.0, size=(n_vortices, 2))
+    radii = rng.uniform(radius_range[0], radius_range[1], size=n_vortices)
+    speeds = rng.uniform(strength_range[0], strength_range[1], size=n_vortices) * u0
+    signs = np.where(rng.integers(0, 2, size=n_vortices) == 0, -1.0, 1.0)
+    c = (np.arange(n, dtype=np.float64) + 0.5) / n
+    for (cx, cy), rk, sk, sg in zip(centres, radii, speeds, signs):
+        dx = c[None, :] - cx
+        dx = dx - np.round(dx)
+        dy = c[:, None] - cy
+        dy = dy - np.round(dy)
+        r2 = dx * dx + dy * dy
+        amp = sg * sk * np.exp(0.5 - r2 / (2.0 * rk * rk)) / rk
+        ux = ux - amp * dy
+        uy = uy + amp * dx
+    return rho, ux, uy

@@ -1,0 +1,196 @@
+"""GPU parity of the learned-threshold path.
+
+* The network's HIP forward pass, gradients and Adam step against the
+  oracle (same bfloat16-rounded weights; float32 accumulation vs float64).
+* Per-patch thresholds: one step from a common state against the oracle with
+  the same per-patch threshold tables.
+* The exported network inputs are the stored coefficients at stride 8.
+* A small end-to-end run (data, training, controlled run, fixed sweep) that
+  reports what the trained network gains over the fixed threshold.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lbmz_learned as NL
+from oracle import lbmz_oracle as O
+from synth import shear_with_vortices
+
+from gpu_helpers import make_ctx, require_gpu, torch  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*args):
+    print("[case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _oracle_params(flat, k):
+    p, off = {}, 0
+    for name, shp in NL.param_shapes(k).items():
+        size = int(np.prod(shp))
+        p[name] = NL.bf16_round(flat[off:off + size]).astype(np.float64).reshape(shp)
+        off += size
+    assert off == flat.size
+    return p
+
+
+def _inputs(b, seed):
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal((b, 9, 8, 8)) * 10.0 ** rng.uniform(-6, -1, (b, 9, 8, 8))).astype(np.float32)
+    x[rng.random(x.shape) < 0.3] = 0
+    return x
+
+
+def _oracle_x(x):
+    return np.arcsinh(x.astype(np.float64) / NL.FEATURE_SCALE)
+
+
+@pytest.mark.parametrize("k", [3, 12])
+def test_forward_matches_oracle(k):
+    from paper_2302_09883_amd import Net
+    from paper_2302_09883_amd.learned import init_params
+    _say("net forward", k)
+    net = Net(k)
+    flat = init_params(k, seed=3)
+    flat[-k:] = np.linspace(-1, 1, k)            # non-zero head biases
+    net.set_params(flat)
+    x = _inputs(40, seed=4)
+    got = net.forward(x)
+    want, _ = NL.forward(_oracle_params(flat, k), _oracle_x(x))
+    assert np.max(np.abs(got - want)) <= 1e-4 * (1 + np.max(np.abs(want)))
+    assert np.allclose(net.params(), flat)        # the master copy is what was set
+
+
+def test_gradients_match_oracle():
+    from paper_2302_09883_amd import Net
+    from paper_2302_09883_amd.learned import init_params
+    _say("net gradients")
+    k = 6
+    net = Net(k)
+    flat = init_params(k, seed=5)
+    rng = np.random.default_rng(6)
+    flat = (flat + 0.02 * rng.standard_normal(flat.size)).astype(np.float32)   # every ReLU branch
+    net.set_params(flat)
+    x = _inputs(37, seed=7)                        # not a multiple of the samples per workgroup
+    t = rng.standard_normal((37, k)).astype(np.float32)
+    g, loss = net.gradients(x, t)
+    p = _oracle_params(flat, k)
+    wl, wg = NL.loss_and_grads(p, _oracle_x(x), t.astype(np.float64))
+    assert abs(loss - wl) <= 1e-4 * abs(wl)
+    off = 0
+    for name, shp in NL.param_shapes(k).items():
+        size = int(np.prod(shp))
+        a = g[off:off + size]
+        b = wg[name].reshape(-1)
+        off += size
+        assert np.linalg.norm(a - b) <= 2e-3 * np.linalg.norm(b) + 1e-7, name
+
+
+def test_adam_step_matches_oracle():
+    from paper_2302_09883_amd import Net
+    from paper_2302_09883_amd.learned import init_params
+    _say("net adam")
+    k = 4
+    net = Net(k)
+    flat = init_params(k, seed=8)
+    net.set_params(flat)
+    x = _inputs(32, seed=9)
+    t = np.random.default_rng(10).standard_normal((32, k)).astype(np.float32)
+    g, _ = net.gradients(x, t)
+    net.train_step(x, t, lr=1e-3)
+    got = net.params()
+    p = {"w": flat.astype(np.float64)}
+    m = {"w": np.zeros(flat.size)}
+    v = {"w": np.zeros(flat.size)}
+    NL.adam_step(p, m, v, {"w": g.astype(np.float64)}, step=1, lr=1e-3)
+    assert np.max(np.abs(got - p["w"])) <= 1e-6
+
+
+def test_training_reduces_the_loss_on_the_gpu():
+    from paper_2302_09883_amd import Net
+    from paper_2302_09883_amd.learned import init_params
+    _say("net training")
+    k = 2
+    x = _inputs(256, seed=11)
+    ox = _oracle_x(x)
+    t = np.stack([ox.std(axis=(1, 2, 3)), ox[:, 0].mean(axis=(1, 2))], axis=1).astype(np.float32)
+    net = Net(k)
+    net.set_params(init_params(k, seed=12))
+    l0 = net.gradients(x, t)[1]
+    for _ in range(80):
+        net.train_step(x, t, lr=3e-3)
+    l1 = net.gradients(x, t)[1]
+    assert l1 < 0.3 * l0
+
+
+def _macro(n, seed):
+    rho, ux, uy = shear_with_vortices(n, seed=seed)
+    return [a.astype(np.float32) for a in (rho, ux, uy)]
+
+
+def test_per_patch_thresholds_one_step_from_common_state():
+    from paper_2302_09883_amd import decode_records
+    _say("per-patch eps")
+    n, p, levels = 256, 64, 5
+    rng = np.random.default_rng(13)
+    eps = 10.0 ** rng.uniform(-5, -2.5, (n // p) ** 2)
+    ctx = make_ctx(n, "d2q9_bgk", "f32", p, "bl53", levels, 1e-4)
+    ctx.set_patch_eps(eps)
+    g = O.Geometry(n, p, O.BL53, levels)
+    twin = O.CompressedRun(g, O.Scheme("d2q9_bgk", tau=0.6), 1e-4, O.RULE_CAPPED, np.float32)
+    twin.set_patch_eps(eps)
+    rho, ux, uy = shear_with_vortices(n, seed=14)
+    twin.set_grid(O.d2q9_equilibrium(rho, ux, uy).astype(np.float32))
+    twin.step(2)
+    table, pool = O.encode_store(twin.coef)
+    ctx.put_store(table, pool)
+    ctx.step(1)
+    twin.step(1)
+    t2, p2 = ctx.store()
+    got = decode_records(t2, p2, g.s, np.float32)
+    want = twin.coef
+    u = np.finfo(np.float32).eps
+    delta = 256 * u * float(np.max(np.abs(twin.grid())))
+    flip = (got != 0) != (want != 0)
+    near = np.abs(np.abs(np.where(got != 0, got, want)) - twin.thr) <= delta
+    assert np.all(near[flip]), int(flip.sum())
+    assert np.max(np.abs(np.where(flip, 0.0, got - want))) <= delta
+    # the thresholds really differ per patch: more kept coefficients where eps is small
+    kept = (got != 0).reshape(got.shape[0], -1).sum(axis=1)
+    assert np.corrcoef(np.log(eps), kept)[0, 1] < 0
+    ctx.set_patch_eps(None)
+
+
+def test_features_are_the_stored_coefficients_at_stride_8():
+    from paper_2302_09883_amd import decode_records
+    _say("features")
+    n = 256
+    ctx = make_ctx(n, "d2q9_bgk", "f32", 64, "bl53", 5, 1e-4)
+    ctx.enable_features(True)
+    ctx.set_macroscopic(*_macro(n, 15))
+    ctx.step(3)
+    feats = ctx.features()
+    table, pool = ctx.store()
+    coef = decode_records(table, pool, 65, np.float32)
+    assert np.array_equal(feats, coef[:, :, 0:64:8, 0:64:8])
+
+
+def test_end_to_end_small():
+    from paper_2302_09883_amd import learned as LRN
+    _say("learned end to end")
+    res = LRN.evaluate(n_train=256, train_seeds=(1, 2), times=(40, 80), n_eval=256, eval_seed=50, steps=100,
+                       epochs=5, fixed=(3e-5,))
+    assert res["samples"] == 2 * 2 * 16
+    r = res["runs"][0]
+    assert np.isfinite(r["learned"]["rel_l2"]) and r["learned"]["ratio_mean"] > 1
+    assert len(res["fixed"]) == LRN.K
+    print("[case] learned small: learned", r["learned"], "fixed ratio at that error",
+          r["fixed_ratio_at_learned_error"], "gain", r["gain"])
