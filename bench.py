@@ -105,13 +105,20 @@ def measured_traffic():
     return int(float(kv["bytes_per_launch"]))
 
 
-def run_point(eps: float, steps: int, warmup: int, macro, ref_state):
+TUNE_STEPS = 3   # steps per autotuner variant (8 x this many steps before the warm-up)
+
+
+def run_point(eps: float, steps: int, warmup: int, macro, ref_state, autotune: bool = True):
     import torch
 
     from paper_2302_09883_amd import Context
 
     ctx = Context(N, scheme="d2q9_bgk", dtype="f32", p=P, wavelet="bl53", levels=LEVELS, eps=eps, tau=TAU)
     ctx.set_macroscopic(*macro)
+    tune_ms = None
+    if autotune:
+        tune_ms = [round(float(v), 5) for v in ctx.autotune(TUNE_STEPS)]
+    mode = ctx.execution()
     ctx.step(warmup)
     s0 = ctx.stats()
     torch.cuda.synchronize()
@@ -145,6 +152,7 @@ def run_point(eps: float, steps: int, warmup: int, macro, ref_state):
         "paper_l2": paper_l2,
         "bytes_per_launch": bytes_launch,
         "regrows": s1["regrows"],
+        "execution": {"persistent": mode[0], "graph": mode[1], "autotune_ms_per_step": tune_ms},
         "mass_drift": (s1["totals"][0] + sum(s1["totals"][1:])) / (s0["totals"][0] + sum(s0["totals"][1:])) - 1.0,
     }
     ctx.close()
@@ -233,6 +241,8 @@ def main():
     ap.add_argument("--eps", type=float, nargs="*", default=[1e-5, 1e-4, 1e-3],
                     help="threshold sweep (eps=1e-4 is always run: it is the headline point)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time one workgroup per patch with plain launches instead of the autotuned mode")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (the reference kernel for counter scaling)")
@@ -251,10 +261,11 @@ def main():
     torch.cuda.set_device(0)
     rho, ux, uy = shear_layer_macroscopic(N, seed=SEED)
     macro = tuple(a.astype(np.float32) for a in (rho, ux, uy))
-    ref_state, ref_mlups = reference_state(macro, args.warmup + args.steps)
+    pre = (8 * TUNE_STEPS if not args.no_autotune else 0) + args.warmup
+    ref_state, ref_mlups = reference_state(macro, pre + args.steps)
 
     eps_list = list(dict.fromkeys(args.eps + [PRIMARY_EPS]))
-    points = [run_point(e, args.steps, args.warmup, macro, ref_state) for e in sorted(eps_list)]
+    points = [run_point(e, args.steps, args.warmup, macro, ref_state, not args.no_autotune) for e in sorted(eps_list)]
     prim = next(p for p in points if p["eps"] == PRIMARY_EPS)
 
     npatch = (N // P) ** 2
@@ -306,7 +317,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "D2Q9 BGK tau=0.6, 2048x2048 periodic, 64x64 patches, folded BL5/3 L=5, "
                                "capped threshold, double shear layer",
-                   "grid": N, "patch": P, "levels": LEVELS, "eps": PRIMARY_EPS, "parallelism": "single GPU"},
+                   "grid": N, "patch": P, "levels": LEVELS, "eps": PRIMARY_EPS, "parallelism": "single GPU",
+                   "execution": prim["execution"]},
         "compression_ratio": round(prim["ratio"], 2),
         "rel_l2_vs_uncompressed": prim["rel_l2"],
         "cr_at_fixed_l2": [cr_at_error(points, t) for t in TARGET_REL_L2],

@@ -224,6 +224,23 @@ int lbmz_stats(lbmz_ctx* ctx, lbmz_stats_t* out);
  * Record placement in the pool is not canonical (any non-overlapping layout
  * is valid); the records themselves are. */
 
+/* ---- execution of the step --------------------------------------------------
+ * persistent = 1: every step runs as one launch of a fixed set of resident
+ * workgroups (as many as the device holds at once) that take patches from a
+ * work queue, instead of one workgroup per patch.  graph = 1: lbmz_step issues
+ * its steps in chunks of six as one HIP graph launch (kernel nodes only; the
+ * arguments of every node are updated before each launch).  Every mode
+ * computes the same records; only their placement in the pool may differ. */
+int lbmz_set_execution(lbmz_ctx* ctx, int persistent, int graph);
+int lbmz_get_execution(lbmz_ctx* ctx, int* persistent, int* graph);
+
+/* Autotuner: runs 2 * steps_per_variant steps in each of the four modes
+ * (advancing the simulation by 8 * steps_per_variant steps; the modes give
+ * identical results), times the second half of each with HIP events, and
+ * keeps the fastest.  ms_out (may be null) receives the four per-step times,
+ * index 2 * persistent + graph. */
+int lbmz_autotune(lbmz_ctx* ctx, int steps_per_variant, float* ms_out);
+
 /* ---- per-patch thresholds and the learned predictor's inputs ------------ */
 
 /* Per-patch threshold constants: eps[q] replaces the context's eps for patch

@@ -1,59 +1,18 @@
-// Kernel instantiations: double, scheme S_FV, patch sizes [8, 16, 32, 64], Haar and BL5/3.
+// Kernel instantiations: double, scheme S_FV (upwind transport), patch sizes [8, 16, 32, 64], Haar and BL5/3, double records.
 #include "lbmz_patch_kernel.h"
 
 namespace lbmz {
 
-bool dispatch_f64_fv(const KernelKey& k, int op, const PatchArgs* a, int npatch, hipStream_t s,
-                       hipError_t* err, size_t* lds) {
-  if (k.dtype != 1 || k.scheme != S_FV || k.vf != VF_F32) return false;
-  if (k.p == 8 && k.wavelet == W_HAAR) {
-    if (op == 0) *err = launch_patch_kernels<double, 8, W_HAAR, S_FV>(true, *a, npatch, s);
-    else if (op == 1) *err = launch_patch_kernels<double, 8, W_HAAR, S_FV>(false, *a, npatch, s);
-    else *lds = patch_lds_bytes<double, 8, W_HAAR, S_FV>();
-    return true;
-  }
-  if (k.p == 8 && k.wavelet == W_BL53) {
-    if (op == 0) *err = launch_patch_kernels<double, 8, W_BL53, S_FV>(true, *a, npatch, s);
-    else if (op == 1) *err = launch_patch_kernels<double, 8, W_BL53, S_FV>(false, *a, npatch, s);
-    else *lds = patch_lds_bytes<double, 8, W_BL53, S_FV>();
-    return true;
-  }
-  if (k.p == 16 && k.wavelet == W_HAAR) {
-    if (op == 0) *err = launch_patch_kernels<double, 16, W_HAAR, S_FV>(true, *a, npatch, s);
-    else if (op == 1) *err = launch_patch_kernels<double, 16, W_HAAR, S_FV>(false, *a, npatch, s);
-    else *lds = patch_lds_bytes<double, 16, W_HAAR, S_FV>();
-    return true;
-  }
-  if (k.p == 16 && k.wavelet == W_BL53) {
-    if (op == 0) *err = launch_patch_kernels<double, 16, W_BL53, S_FV>(true, *a, npatch, s);
-    else if (op == 1) *err = launch_patch_kernels<double, 16, W_BL53, S_FV>(false, *a, npatch, s);
-    else *lds = patch_lds_bytes<double, 16, W_BL53, S_FV>();
-    return true;
-  }
-  if (k.p == 32 && k.wavelet == W_HAAR) {
-    if (op == 0) *err = launch_patch_kernels<double, 32, W_HAAR, S_FV>(true, *a, npatch, s);
-    else if (op == 1) *err = launch_patch_kernels<double, 32, W_HAAR, S_FV>(false, *a, npatch, s);
-    else *lds = patch_lds_bytes<double, 32, W_HAAR, S_FV>();
-    return true;
-  }
-  if (k.p == 32 && k.wavelet == W_BL53) {
-    if (op == 0) *err = launch_patch_kernels<double, 32, W_BL53, S_FV>(true, *a, npatch, s);
-    else if (op == 1) *err = launch_patch_kernels<double, 32, W_BL53, S_FV>(false, *a, npatch, s);
-    else *lds = patch_lds_bytes<double, 32, W_BL53, S_FV>();
-    return true;
-  }
-  if (k.p == 64 && k.wavelet == W_HAAR) {
-    if (op == 0) *err = launch_patch_kernels<double, 64, W_HAAR, S_FV>(true, *a, npatch, s);
-    else if (op == 1) *err = launch_patch_kernels<double, 64, W_HAAR, S_FV>(false, *a, npatch, s);
-    else *lds = patch_lds_bytes<double, 64, W_HAAR, S_FV>();
-    return true;
-  }
-  if (k.p == 64 && k.wavelet == W_BL53) {
-    if (op == 0) *err = launch_patch_kernels<double, 64, W_BL53, S_FV>(true, *a, npatch, s);
-    else if (op == 1) *err = launch_patch_kernels<double, 64, W_BL53, S_FV>(false, *a, npatch, s);
-    else *lds = patch_lds_bytes<double, 64, W_BL53, S_FV>();
-    return true;
-  }
+bool dispatch_f64_fv(LBMZ_DISPATCH_ARGS) {
+  if (k.dtype != 1 || k.scheme != S_FV) return false;
+  LBMZ_CASE_T(double, 8, W_HAAR, S_FV, VF_F32)
+  LBMZ_CASE_T(double, 8, W_BL53, S_FV, VF_F32)
+  LBMZ_CASE_T(double, 16, W_HAAR, S_FV, VF_F32)
+  LBMZ_CASE_T(double, 16, W_BL53, S_FV, VF_F32)
+  LBMZ_CASE_T(double, 32, W_HAAR, S_FV, VF_F32)
+  LBMZ_CASE_T(double, 32, W_BL53, S_FV, VF_F32)
+  LBMZ_CASE_T(double, 64, W_HAAR, S_FV, VF_F32)
+  LBMZ_CASE_T(double, 64, W_BL53, S_FV, VF_F32)
   return false;
 }
 

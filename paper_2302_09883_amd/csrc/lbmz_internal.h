@@ -26,6 +26,8 @@ struct Ctrl {
   unsigned long long top16[3];   // pool bump counters (16-byte units), rotated by epoch % 3
   unsigned int abort;            // bit 0: pool overflow, bit 1: non-finite coefficient
   unsigned int abort_epoch;      // smallest epoch that raised a flag (0xffffffff = none)
+  unsigned int queue[3];         // persistent step: next patch to take, rotated by epoch % 3
+  unsigned int pad;
 };
 
 constexpr unsigned int ABORT_OVERFLOW = 1u;
@@ -79,10 +81,20 @@ struct KernelKey {
 // Launch the fused step kernel (time n -> n + 1) or the auxiliary kernel.
 // Return hipErrorInvalidValue when no kernel is compiled for the key.
 hipError_t launch_step(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s);
+hipError_t launch_step_persistent(const KernelKey& k, const PatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_aux(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s);
 bool have_kernel(const KernelKey& k);
 // LDS bytes used by the kernels of a key (0 if not compiled).
 size_t kernel_lds_bytes(const KernelKey& k);
+// Entry of the step kernel (persistent or one workgroup per patch) and its
+// workgroup size, for graph kernel nodes.
+const void* step_kernel_entry(const KernelKey& k, bool persistent);
+int kernel_threads(const KernelKey& k);
+
+// Dispatch of one compiled kernel family: true when the key is compiled in
+// this unit; `out` receives the operation's result (see dispatch_op).
+#define LBMZ_DISPATCH_ARGS const KernelKey& k, int op, const PatchArgs* a, int grid, hipStream_t s, \
+                           hipError_t* err, size_t* out
 
 // Dense (uncompressed) reference step on a periodic [nfields][n][n] grid.
 hipError_t launch_reference_step(int dtype, int scheme, const void* in, void* out, int n,

@@ -1244,22 +1244,9 @@ __device__ __forceinline__ bool compact_any(const PatchArgs& a, int q, SM& sm) {
   else return column_compact_q<C, T, WAV, FWD, VF>(a, q, sm);
 }
 
-// One step (time n -> n + 1) of patch blockIdx.x.
-template <class T, int P, int WAV, int SCH, int VF = VF_F32>
-__global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(PatchArgs a) {
-  using C = Cfg<T, P, WAV, SCH>;
-  __shared__ Smem<C, T, VF> sm;
-  const int q = blockIdx.x;
-  if (threadIdx.x == 0) {
-    // Stop if an earlier launch of this batch failed (its input is the last
-    // good state); a failure inside this launch lets every patch finish so
-    // that the pool counter ends at the exact size the step needs.
-    const bool stop = a.ctrl->abort != 0u && a.ctrl->abort_epoch < a.epoch;
-    sm.misc[2] = stop ? 1u : 0u;
-    if (!stop && q == 0) a.ctrl->top16[(a.epoch + 1u) % 3u] = 0ull;
-  }
-  __syncthreads();
-  if (sm.misc[2] != 0u) return;
+// One step (time n -> n + 1) of patch q, S1..S9.
+template <class C, class T, int WAV, int SCH, int VF, class SM>
+__device__ __forceinline__ void step_one_patch(const PatchArgs& a, int q, SM& sm) {
   LBMZ_MARK(0);
   if constexpr (SCH == S_LBM) gather_lbm<C, T>(a, q, sm.tile, sm.ghost);
   else gather_fv<C, T>(a, q, sm.ghost);
@@ -1280,6 +1267,50 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(P
     LBMZ_MARK(5);
     row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
     LBMZ_MARK(6);
+  }
+}
+
+// Stop if an earlier launch of this batch failed (its input is the last good
+// state); a failure inside this launch lets every patch finish so that the
+// pool counter ends at the exact size the step needs.  The workgroup that
+// resets the next launch's counters is chosen by the caller.
+template <class SM>
+__device__ __forceinline__ bool step_stops(const PatchArgs& a, bool reset_next, SM& sm) {
+  if (threadIdx.x == 0) {
+    const bool stop = a.ctrl->abort != 0u && a.ctrl->abort_epoch < a.epoch;
+    sm.misc[2] = stop ? 1u : 0u;
+    if (!stop && reset_next) {
+      a.ctrl->top16[(a.epoch + 1u) % 3u] = 0ull;
+      a.ctrl->queue[(a.epoch + 1u) % 3u] = 0u;
+    }
+  }
+  __syncthreads();
+  return sm.misc[2] != 0u;
+}
+
+// One step of patch blockIdx.x (one workgroup per patch).
+template <class T, int P, int WAV, int SCH, int VF = VF_F32>
+__global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(PatchArgs a) {
+  using C = Cfg<T, P, WAV, SCH>;
+  __shared__ Smem<C, T, VF> sm;
+  if (step_stops(a, blockIdx.x == 0, sm)) return;
+  step_one_patch<C, T, WAV, SCH, VF>(a, blockIdx.x, sm);
+}
+
+// One step of every patch by a fixed set of resident workgroups that take
+// patches from a work queue (an atomic counter) until none is left.
+template <class T, int P, int WAV, int SCH, int VF = VF_F32>
+__global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_persistent_kernel(PatchArgs a) {
+  using C = Cfg<T, P, WAV, SCH>;
+  __shared__ Smem<C, T, VF> sm;
+  if (step_stops(a, blockIdx.x == 0, sm)) return;
+  for (;;) {
+    if (threadIdx.x == 0) sm.misc[3] = atomicAdd(&a.ctrl->queue[a.epoch % 3u], 1u);
+    __syncthreads();
+    const int q = (int)sm.misc[3];
+    if (q >= a.npatch) break;
+    step_one_patch<C, T, WAV, SCH, VF>(a, q, sm);
+    __syncthreads();
   }
 }
 
@@ -1332,18 +1363,49 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
 }
 
 template <class T, int P, int WAV, int SCH, int VF = VF_F32>
-hipError_t launch_patch_kernels(bool step, const PatchArgs& a, int npatch, hipStream_t s) {
-  using C = Cfg<T, P, WAV, SCH>;
-  if (step)
-    hipLaunchKernelGGL((patch_step_kernel<T, P, WAV, SCH, VF>), dim3(npatch), dim3(C::NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((patch_aux_kernel<T, P, WAV, SCH, VF>), dim3(npatch), dim3(C::NT), 0, s, a);
-  return hipGetLastError();
-}
-
-template <class T, int P, int WAV, int SCH, int VF = VF_F32>
 constexpr size_t patch_lds_bytes() {
   return sizeof(Smem<Cfg<T, P, WAV, SCH>, T, VF>);
 }
+
+// Operations of one compiled kernel family (see the dispatch of the runtime):
+// 0 step (one workgroup per patch), 1 auxiliary kernel, 2 LDS bytes,
+// 3 persistent step on `grid` workgroups, 4 / 5 the step / persistent kernel's
+// entry (for graph nodes), 6 threads per workgroup.
+template <class T, int P, int WAV, int SCH, int VF>
+size_t dispatch_op(int op, const PatchArgs* a, int grid, hipStream_t s, hipError_t* err) {
+  using C = Cfg<T, P, WAV, SCH>;
+  switch (op) {
+    case 0:
+      hipLaunchKernelGGL((patch_step_kernel<T, P, WAV, SCH, VF>), dim3(grid), dim3(C::NT), 0, s, *a);
+      *err = hipGetLastError();
+      return 0;
+    case 1:
+      hipLaunchKernelGGL((patch_aux_kernel<T, P, WAV, SCH, VF>), dim3(grid), dim3(C::NT), 0, s, *a);
+      *err = hipGetLastError();
+      return 0;
+    case 2:
+      return patch_lds_bytes<T, P, WAV, SCH, VF>();
+    case 3:
+      hipLaunchKernelGGL((patch_step_persistent_kernel<T, P, WAV, SCH, VF>), dim3(grid), dim3(C::NT), 0, s, *a);
+      *err = hipGetLastError();
+      return 0;
+    case 4:
+      return reinterpret_cast<size_t>(reinterpret_cast<const void*>(&patch_step_kernel<T, P, WAV, SCH, VF>));
+    case 5:
+      return reinterpret_cast<size_t>(
+          reinterpret_cast<const void*>(&patch_step_persistent_kernel<T, P, WAV, SCH, VF>));
+    case 6:
+      return (size_t)C::NT;
+    default:
+      *err = hipErrorInvalidValue;
+      return 0;
+  }
+}
+
+#define LBMZ_CASE_T(T_, P_, W_, S_, V_)                                      \
+  if (k.p == P_ && k.wavelet == W_ && k.vf == V_) {                          \
+    *out = dispatch_op<T_, P_, W_, S_, V_>(op, a, grid, s, err);             \
+    return true;                                                             \
+  }
 
 }  // namespace lbmz

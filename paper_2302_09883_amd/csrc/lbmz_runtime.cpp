@@ -22,40 +22,62 @@
 #include "lbmz_internal.h"
 
 namespace lbmz {
-bool dispatch_f32_fv(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
-bool dispatch_f32_lbm(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
-bool dispatch_f64_fv(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
-bool dispatch_f64_lbm(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
-bool dispatch_f32_fv_q(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
-bool dispatch_f32_lbm_q(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
-bool dispatch_f32_euler(const KernelKey&, int, const PatchArgs*, int, hipStream_t, hipError_t*, size_t*);
+bool dispatch_f32_fv(LBMZ_DISPATCH_ARGS);
+bool dispatch_f32_lbm(LBMZ_DISPATCH_ARGS);
+bool dispatch_f64_fv(LBMZ_DISPATCH_ARGS);
+bool dispatch_f64_lbm(LBMZ_DISPATCH_ARGS);
+bool dispatch_f32_fv_q(LBMZ_DISPATCH_ARGS);
+bool dispatch_f32_lbm_q(LBMZ_DISPATCH_ARGS);
+bool dispatch_f32_euler(LBMZ_DISPATCH_ARGS);
 
-static bool dispatch(const KernelKey& k, int op, const PatchArgs* a, int npatch, hipStream_t s,
-                     hipError_t* err, size_t* lds) {
-  return dispatch_f32_fv(k, op, a, npatch, s, err, lds) || dispatch_f32_lbm(k, op, a, npatch, s, err, lds) ||
-         dispatch_f64_fv(k, op, a, npatch, s, err, lds) || dispatch_f64_lbm(k, op, a, npatch, s, err, lds) ||
-         dispatch_f32_fv_q(k, op, a, npatch, s, err, lds) || dispatch_f32_lbm_q(k, op, a, npatch, s, err, lds) ||
-         dispatch_f32_euler(k, op, a, npatch, s, err, lds);
+static bool dispatch(LBMZ_DISPATCH_ARGS) {
+  return dispatch_f32_fv(k, op, a, grid, s, err, out) || dispatch_f32_lbm(k, op, a, grid, s, err, out) ||
+         dispatch_f64_fv(k, op, a, grid, s, err, out) || dispatch_f64_lbm(k, op, a, grid, s, err, out) ||
+         dispatch_f32_fv_q(k, op, a, grid, s, err, out) || dispatch_f32_lbm_q(k, op, a, grid, s, err, out) ||
+         dispatch_f32_euler(k, op, a, grid, s, err, out);
+}
+
+static size_t dispatch_op_of(const KernelKey& k, int op, const PatchArgs* a, int grid, hipStream_t s,
+                             hipError_t* err) {
+  size_t out = 0;
+  if (!dispatch(k, op, a, grid, s, err, &out)) *err = hipErrorInvalidValue;
+  return out;
 }
 
 hipError_t launch_step(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s) {
-  hipError_t e = hipErrorInvalidValue;
-  size_t lds = 0;
-  dispatch(k, 0, &a, npatch, s, &e, &lds);
+  hipError_t e = hipSuccess;
+  dispatch_op_of(k, 0, &a, npatch, s, &e);
+  return e;
+}
+
+hipError_t launch_step_persistent(const KernelKey& k, const PatchArgs& a, int grid, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  dispatch_op_of(k, 3, &a, grid, s, &e);
   return e;
 }
 
 hipError_t launch_aux(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s) {
-  hipError_t e = hipErrorInvalidValue;
-  size_t lds = 0;
-  dispatch(k, 1, &a, npatch, s, &e, &lds);
+  hipError_t e = hipSuccess;
+  dispatch_op_of(k, 1, &a, npatch, s, &e);
   return e;
 }
 
 size_t kernel_lds_bytes(const KernelKey& k) {
   hipError_t e = hipSuccess;
-  size_t lds = 0;
-  return dispatch(k, 2, nullptr, 0, nullptr, &e, &lds) ? lds : 0;
+  const size_t v = dispatch_op_of(k, 2, nullptr, 0, nullptr, &e);
+  return e == hipSuccess ? v : 0;
+}
+
+const void* step_kernel_entry(const KernelKey& k, bool persistent) {
+  hipError_t e = hipSuccess;
+  const size_t v = dispatch_op_of(k, persistent ? 5 : 4, nullptr, 0, nullptr, &e);
+  return e == hipSuccess ? reinterpret_cast<const void*>(v) : nullptr;
+}
+
+int kernel_threads(const KernelKey& k) {
+  hipError_t e = hipSuccess;
+  const size_t v = dispatch_op_of(k, 6, nullptr, 0, nullptr, &e);
+  return e == hipSuccess ? (int)v : 0;
 }
 
 bool have_kernel(const KernelKey& k) { return kernel_lds_bytes(k) != 0; }
@@ -69,6 +91,13 @@ struct lbmz_ctx {
   size_t esize = 4;
   int n = 0, p = 0, npx = 0, npatch = 0, s = 0, levels = 0, wavelet = 0, rule = 0, scheme = 0;
   int vf = VF_F32;   // ValueFormat of the records
+  // execution of the step: persistent work-queue kernel, hipGraph chunks
+  int exec_persistent = 0, exec_graph = 0, persist_grid = 0;
+  hipGraph_t graph[2] = {nullptr, nullptr};      // GRAPH_STEPS launches from buffer parity 0 / 1
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraphNode_t gnode[2][6] = {};
+  int graph_mode[2] = {-1, -1};                  // exec_persistent at instantiation
+  PatchArgs gargs[6] = {};
   double* eps_patch = nullptr;   // per-patch thresholds (device), or null
   float* features = nullptr;     // per-patch network inputs of the last step (device), or null
   bool features_valid = false;
@@ -401,6 +430,75 @@ int validate_common(const lbmz_grid* g, const lbmz_scheme* sc, lbmz_ctx* c) {
   return LBMZ_OK;
 }
 
+constexpr int GRAPH_STEPS = 6;   // a whole number of buffer swaps (2) and counter rotations (3)
+
+void drop_graphs(lbmz_ctx* c) {
+  for (int b = 0; b < 2; ++b) {
+    if (c->gexec[b]) (void)hipGraphExecDestroy(c->gexec[b]);
+    if (c->graph[b]) (void)hipGraphDestroy(c->graph[b]);
+    c->gexec[b] = nullptr;
+    c->graph[b] = nullptr;
+    c->graph_mode[b] = -1;
+  }
+}
+
+int step_grid(lbmz_ctx* c) { return c->exec_persistent ? c->persist_grid : c->npatch; }
+
+// Arguments of the six launches of a graph chunk starting at buffer parity `par`.
+void chunk_args(lbmz_ctx* c, int par, unsigned e0) {
+  for (int i = 0; i < GRAPH_STEPS; ++i) {
+    const int in = par ^ (i & 1);
+    c->gargs[i] = args_for(c, in, in ^ 1, e0 + (unsigned)i);
+  }
+}
+
+hipKernelNodeParams node_params(lbmz_ctx* c, int i, void** slot) {
+  hipKernelNodeParams p{};
+  p.func = const_cast<void*>(step_kernel_entry(c->key, c->exec_persistent != 0));
+  p.gridDim = dim3((unsigned)step_grid(c));
+  p.blockDim = dim3((unsigned)kernel_threads(c->key));
+  p.sharedMemBytes = 0;
+  slot[0] = &c->gargs[i];
+  p.kernelParams = slot;
+  p.extra = nullptr;
+  return p;
+}
+
+// Launch GRAPH_STEPS steps from buffer parity `par` with epochs e0.. as one graph.
+int launch_chunk(lbmz_ctx* c, int par, unsigned e0) {
+  chunk_args(c, par, e0);
+  void* slots[GRAPH_STEPS][1];
+  if (!c->gexec[par] || c->graph_mode[par] != c->exec_persistent) {
+    if (c->gexec[par]) (void)hipGraphExecDestroy(c->gexec[par]);
+    if (c->graph[par]) (void)hipGraphDestroy(c->graph[par]);
+    c->gexec[par] = nullptr;
+    c->graph[par] = nullptr;
+    HIPCHK(c, hipGraphCreate(&c->graph[par], 0));
+    for (int i = 0; i < GRAPH_STEPS; ++i) {
+      hipKernelNodeParams p = node_params(c, i, slots[i]);
+      if (!p.func) return fail(c, LBMZ_EINVAL, "no step kernel for this configuration");
+      hipGraphNode_t* dep = i ? &c->gnode[par][i - 1] : nullptr;
+      HIPCHK(c, hipGraphAddKernelNode(&c->gnode[par][i], c->graph[par], dep, i ? 1 : 0, &p));
+    }
+    HIPCHK(c, hipGraphInstantiate(&c->gexec[par], c->graph[par], nullptr, nullptr, 0));
+    c->graph_mode[par] = c->exec_persistent;
+  } else {
+    for (int i = 0; i < GRAPH_STEPS; ++i) {
+      hipKernelNodeParams p = node_params(c, i, slots[i]);
+      HIPCHK(c, hipGraphExecKernelNodeSetParams(c->gexec[par], c->gnode[par][i], &p));
+    }
+  }
+  HIPCHK(c, hipGraphLaunch(c->gexec[par], c->stream));
+  return LBMZ_OK;
+}
+
+int launch_one(lbmz_ctx* c, int in, unsigned e) {
+  PatchArgs a = args_for(c, in, in ^ 1, e);
+  if (c->exec_persistent) HIPCHK(c, launch_step_persistent(c->key, a, c->persist_grid, c->stream));
+  else HIPCHK(c, launch_step(c->key, a, c->npatch, c->stream));
+  return LBMZ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -617,11 +715,18 @@ int lbmz_step(lbmz_ctx* c, int n) {
     if (attempt > 64) return fail(c, LBMZ_EOVERFLOW, "pool kept overflowing");
     const unsigned e0 = c->epoch_next;
     const int cur0 = c->cur;
-    for (int k = 0; k < remaining; ++k) {
-      const unsigned e = c->epoch_next++;
-      PatchArgs a = args_for(c, c->cur, c->cur ^ 1, e);
-      HIPCHK(c, launch_step(c->key, a, c->npatch, c->stream));
-      c->cur ^= 1;
+    for (int k = 0; k < remaining;) {
+      if (c->exec_graph && remaining - k >= GRAPH_STEPS) {
+        rc = launch_chunk(c, c->cur, c->epoch_next);
+        if (rc) return rc;
+        c->epoch_next += GRAPH_STEPS;
+        k += GRAPH_STEPS;   // an even number of swaps: the parity is unchanged
+      } else {
+        rc = launch_one(c, c->cur, c->epoch_next++);
+        if (rc) return rc;
+        c->cur ^= 1;
+        ++k;
+      }
     }
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     rc = read_ctrl(c);
@@ -955,11 +1060,62 @@ int lbmz_get_features(lbmz_ctx* c, float* dst, size_t bytes, int dst_on_device) 
   return LBMZ_OK;
 }
 
+int lbmz_set_execution(lbmz_ctx* c, int persistent, int graph) {
+  if (!c) return LBMZ_EINVAL;
+  if (c->reference) return LBMZ_OK;
+  if ((persistent != 0 && persistent != 1) || (graph != 0 && graph != 1))
+    return fail(c, LBMZ_EINVAL, "execution flags must be 0 or 1");
+  if (persistent && c->persist_grid <= 0) {
+    int ncu = 0, per_cu = 0;
+    HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+    const void* fn = step_kernel_entry(c->key, true);
+    if (!fn) return fail(c, LBMZ_EINVAL, "no persistent kernel for this configuration");
+    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kernel_threads(c->key), 0));
+    c->persist_grid = std::max(1, std::min(c->npatch, ncu * std::max(1, per_cu)));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->exec_persistent = persistent;
+  c->exec_graph = graph;
+  return LBMZ_OK;
+}
+
+int lbmz_get_execution(lbmz_ctx* c, int* persistent, int* graph) {
+  if (!c || !persistent || !graph) return LBMZ_EINVAL;
+  *persistent = c->exec_persistent;
+  *graph = c->exec_graph;
+  return LBMZ_OK;
+}
+
+int lbmz_autotune(lbmz_ctx* c, int steps_per_variant, float* ms_out) {
+  if (!c || steps_per_variant < 1) return LBMZ_EINVAL;
+  if (c->reference) return LBMZ_OK;
+  float best = 0.f;
+  int bp = 0, bg = 0;
+  for (int v = 0; v < 4; ++v) {
+    const int pv = v >> 1, gv = v & 1;
+    int rc = lbmz_set_execution(c, pv, gv);
+    if (rc) return rc;
+    rc = lbmz_step(c, steps_per_variant);   // warms the variant (graph instantiation)
+    if (rc) return rc;
+    rc = lbmz_step(c, steps_per_variant);
+    if (rc) return rc;
+    const float ms = c->ms_last / (float)steps_per_variant;
+    if (ms_out) ms_out[v] = ms;
+    if (v == 0 || ms < best) {
+      best = ms;
+      bp = pv;
+      bg = gv;
+    }
+  }
+  return lbmz_set_execution(c, bp, bg);
+}
+
 const char* lbmz_last_error(const lbmz_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 void lbmz_destroy(lbmz_ctx* c) {
   if (!c) return;
   if (c->allocated) (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
   for (int b = 0; b < 2; ++b) {
     dfree(c, c->pool[b]);
     dfree(c, c->table[b]);

@@ -86,6 +86,9 @@ def library() -> ct.CDLL:
         "lbmz_get_store": ([vp, vp, vp, ct.c_size_t], ct.c_int),
         "lbmz_put_store": ([vp, vp, vp, ct.c_size_t], ct.c_int),
         "lbmz_set_coefficients": ([vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
+        "lbmz_set_execution": ([vp, ct.c_int, ct.c_int], ct.c_int),
+        "lbmz_get_execution": ([vp, P(ct.c_int), P(ct.c_int)], ct.c_int),
+        "lbmz_autotune": ([vp, ct.c_int, vp], ct.c_int),
         "lbmz_set_patch_eps": ([vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
         "lbmz_enable_features": ([vp, ct.c_int], ct.c_int),
         "lbmz_get_features": ([vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
@@ -223,6 +226,21 @@ class Context:
         ptr, nb, dev, keep = _buffer(coef, self.np_dtype)
         self._check(self._lib.lbmz_set_coefficients(self._h, ptr, nb, dev))
         del keep
+
+    def set_execution(self, persistent: bool = False, graph: bool = False):
+        self._check(self._lib.lbmz_set_execution(self._h, int(bool(persistent)), int(bool(graph))))
+
+    def execution(self):
+        p, g = ct.c_int(), ct.c_int()
+        self._check(self._lib.lbmz_get_execution(self._h, ct.byref(p), ct.byref(g)))
+        return bool(p.value), bool(g.value)
+
+    def autotune(self, steps_per_variant: int = 5):
+        """Pick the fastest execution mode on the current state (advances 8 x steps_per_variant steps);
+        returns the four measured ms per step, index 2 * persistent + graph."""
+        ms = np.zeros(4, dtype=np.float32)
+        self._check(self._lib.lbmz_autotune(self._h, int(steps_per_variant), ct.c_void_p(ms.ctypes.data)))
+        return ms
 
     def set_patch_eps(self, eps=None):
         """Per-patch thresholds ``[npatch]`` (float64, host or device), or None for the single eps."""
