@@ -121,6 +121,7 @@ struct Smem {
   uint32_t ismask[C::M];
   uint32_t vb[C::M];
   uint32_t rb[C::M];
+  uint32_t te[2 * C::M];                 // offset-table entries of the patch being expanded
   unsigned misc[4];
   typename std::conditional<VF == VF_F32, NoLds, NarrowLds<C>>::type nq;
 };
@@ -844,6 +845,13 @@ static __device__ unsigned long long lbmz_phase_clock[4096 * 16];
   } while (0)
 #endif
 
+// Offset-table entries of patch q into LDS (read by the expansion after the
+// next barrier); issued early so that their latency overlaps other loads.
+template <class C, class SM>
+__device__ __forceinline__ void prefetch_table(const PatchArgs& a, int q, SM& sm) {
+  if (threadIdx.x < 2 * C::M) sm.te[threadIdx.x] = a.table_in[2 * (size_t)q * C::M + threadIdx.x];
+}
+
 // ---------------------------------------------------------------------------
 // S1 (+ the column half of S2): records -> inverse-transformed columns in LDS
 // ---------------------------------------------------------------------------
@@ -860,7 +868,10 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
   const int lane = lane_id();
   const int wave = wave_id();
   const int L = a.levels;
-  const uint32_t* te = a.table_in + 2 * (size_t)q * C::M;
+  // offset-table entries, loaded into LDS by prefetch_table before the last barrier
+  // te: wave-uniform index (one scalar value), tel: index that varies over the lanes
+  auto te = [&sm](int i) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)sm.te[i]); };
+  auto tel = [&sm](int i) { return sm.te[i]; };
   const uint8_t* pool = a.pool_in;
 
   // Index-list records: the helper waves (no line in the passes) load their
@@ -872,7 +883,7 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
   if (helper) {
 #pragma unroll
     for (int f = 0; f < C::M; ++f) {
-      const uint32_t w = te[2 * f + 1];
+      const uint32_t w = te(2 * f + 1);
       const uint32_t nnz = w & ~MASK_BIT;
 #pragma unroll
       for (int u = 0; u < C::LPT; ++u) {
@@ -880,7 +891,7 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
         lv[f][u] = T(0);
       }
       if (!(w & MASK_BIT)) {
-        const uint8_t* rec = pool + 16ull * te[2 * f];
+        const uint8_t* rec = pool + 16ull * te(2 * f);
         const uint16_t* idx = reinterpret_cast<const uint16_t*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
 #pragma unroll
         for (int u = 0; u < C::LPT; ++u) {
@@ -898,10 +909,10 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
   // Bitmask records, owned columns (waves 0..M-1).
   if (wave < C::M) {
     const int f = wave;
-    const uint32_t w = te[2 * f + 1];
+    const uint32_t w = te(2 * f + 1);
     if (w & MASK_BIT) {
       const uint32_t nnz = w & ~MASK_BIT;
-      const uint8_t* rec = pool + 16ull * te[2 * f];
+      const uint8_t* rec = pool + 16ull * te(2 * f);
       const T* vals = reinterpret_cast<const T*>(rec);
       const unsigned long long* words =
           reinterpret_cast<const unsigned long long*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
@@ -939,10 +950,10 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
   // Bitmask records, the shared column x = P (wave M, lane = field).
   if (C::RIM && wave == C::M && lane < C::M) {
     const int f = lane;
-    const uint32_t w = te[2 * f + 1];
+    const uint32_t w = tel(2 * f + 1);
     if (w & MASK_BIT) {
       const uint32_t nnz = w & ~MASK_BIT;
-      const uint8_t* rec = pool + 16ull * te[2 * f];
+      const uint8_t* rec = pool + 16ull * tel(2 * f);
       const T* vals = reinterpret_cast<const T*>(rec);
       const unsigned long long* words =
           reinterpret_cast<const unsigned long long*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
@@ -988,11 +999,11 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
   LBMZ_MARK(13);
   bool any_list = false;
 #pragma unroll
-  for (int g = 0; g < C::M; ++g) any_list |= !(te[2 * g + 1] & MASK_BIT);
+  for (int g = 0; g < C::M; ++g) any_list |= !(te(2 * g + 1) & MASK_BIT);
   if (any_list) {
     int f, x;
     const bool line = pass_line<C>(f, x);
-    const bool act = line && !(te[2 * f + 1] & MASK_BIT);
+    const bool act = line && !(tel(2 * f + 1) & MASK_BIT);
     double part = 0.0;
     if (act) {
       T v[C::S];
@@ -1003,7 +1014,7 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
     }
     if constexpr (TOT) {
       if (wave < C::M) {
-        if (!(te[2 * wave + 1] & MASK_BIT)) totals_partial<C, T>(part, sm);
+        if (!(te(2 * wave + 1) & MASK_BIT)) totals_partial<C, T>(part, sm);
       } else if (act) {
         sm.totface[f] = part;
       }
@@ -1244,12 +1255,19 @@ __device__ __forceinline__ bool compact_any(const PatchArgs& a, int q, SM& sm) {
   else return column_compact_q<C, T, WAV, FWD, VF>(a, q, sm);
 }
 
-// One step (time n -> n + 1) of patch q, S1..S9.
+// The loads that start a patch, issued before the barrier that precedes the
+// expansion: the ghost values (S3) and the offset-table entries.
+template <class C, class T, int SCH, class SM>
+__device__ __forceinline__ void begin_patch(const PatchArgs& a, int q, SM& sm) {
+  prefetch_table<C>(a, q, sm);
+  if constexpr (SCH == S_LBM) gather_lbm<C, T>(a, q, sm.tile, sm.ghost);
+  else gather_fv<C, T>(a, q, sm.ghost);
+}
+
+// One step (time n -> n + 1) of patch q, S1..S9, after begin_patch and a barrier.
 template <class C, class T, int WAV, int SCH, int VF, class SM>
 __device__ __forceinline__ void step_one_patch(const PatchArgs& a, int q, SM& sm) {
   LBMZ_MARK(0);
-  if constexpr (SCH == S_LBM) gather_lbm<C, T>(a, q, sm.tile, sm.ghost);
-  else gather_fv<C, T>(a, q, sm.ghost);
   LBMZ_MARK(14);
   expand_any<C, T, WAV, false, VF>(a, q, sm);
   LBMZ_MARK(1);
@@ -1293,6 +1311,7 @@ template <class T, int P, int WAV, int SCH, int VF = VF_F32>
 __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(PatchArgs a) {
   using C = Cfg<T, P, WAV, SCH>;
   __shared__ Smem<C, T, VF> sm;
+  begin_patch<C, T, SCH>(a, blockIdx.x, sm);
   if (step_stops(a, blockIdx.x == 0, sm)) return;
   step_one_patch<C, T, WAV, SCH, VF>(a, blockIdx.x, sm);
 }
@@ -1309,6 +1328,8 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_persiste
     __syncthreads();
     const int q = (int)sm.misc[3];
     if (q >= a.npatch) break;
+    begin_patch<C, T, SCH>(a, q, sm);
+    __syncthreads();
     step_one_patch<C, T, WAV, SCH, VF>(a, q, sm);
     __syncthreads();
   }
@@ -1352,6 +1373,8 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
     row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
     return;
   }
+  prefetch_table<C>(a, q, sm);
+  __syncthreads();
   if (a.mode == AUX_RESTORE) {
     expand_any<C, T, WAV, true, VF>(a, q, sm);
     totals_finish<C, T, false>(a, a.partials_out + (size_t)q * C::M, a.levels, sm);

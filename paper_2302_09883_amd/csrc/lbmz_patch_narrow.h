@@ -424,15 +424,17 @@ __device__ __forceinline__ void expand_columns_q(const PatchArgs& a, int q, SM& 
   const int L1 = L + 1;
   const int SC = ((C::S - 1) >> L) + 1;
   const int NS = SC * SC;
-  const uint32_t* te = a.table_in + 2 * (size_t)q * C::M;
+  // te: wave-uniform index (one scalar value), tel: index that varies over the lanes
+  auto te = [&sm](int i) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)sm.te[i]); };
+  auto tel = [&sm](int i) { return sm.te[i]; };
   const uint8_t* pool = a.pool_in;
 
 #pragma unroll
   for (int f = 0; f < C::M; ++f) zero_span<T>(sm.tile + C::Lay::fb(f), C::S * C::RS, tid, C::NT);
   if (tid < C::M) {
     const int g = tid;
-    const uint32_t ndet = te[2 * g + 1] & ~MASK_BIT;
-    const uint8_t* rec = pool + 16ull * te[2 * g];
+    const uint32_t ndet = tel(2 * g + 1) & ~MASK_BIT;
+    const uint8_t* rec = pool + 16ull * tel(2 * g);
     const unsigned long long occ = *reinterpret_cast<const unsigned long long*>(rec);
     const uint32_t nocc = (uint32_t)__popcll(occ);
     const uint32_t hb = (8u + 4u * nocc + 7u) & ~7u;
@@ -447,10 +449,10 @@ __device__ __forceinline__ void expand_columns_q(const PatchArgs& a, int q, SM& 
   }
   if (wave < C::M) {
     const int g = wave;
-    const uint32_t w = te[2 * g + 1];
+    const uint32_t w = te(2 * g + 1);
     if (w & MASK_BIT) {
       const uint32_t ndet = w & ~MASK_BIT;
-      const uint8_t* rec = pool + 16ull * te[2 * g];
+      const uint8_t* rec = pool + 16ull * te(2 * g);
       const uint32_t nocc = (uint32_t)__popcll(*reinterpret_cast<const unsigned long long*>(rec));
       const uint32_t vb = ((8u + 4u * nocc + 7u) & ~7u) + ((4u * (uint32_t)NS + 7u) & ~7u) +
                           ((ndet * (uint32_t)BY + 7u) & ~7u);
@@ -469,14 +471,14 @@ __device__ __forceinline__ void expand_columns_q(const PatchArgs& a, int q, SM& 
   int pre[C::M + 1];
   pre[0] = 0;
 #pragma unroll
-  for (int g = 0; g < C::M; ++g) pre[g + 1] = pre[g] + NS + (int)(te[2 * g + 1] & ~MASK_BIT);
+  for (int g = 0; g < C::M; ++g) pre[g + 1] = pre[g] + NS + (int)(te(2 * g + 1) & ~MASK_BIT);
   for (int i = tid; i < pre[C::M]; i += C::NT) {
     int g = 0;
 #pragma unroll
     for (int h = 1; h < C::M; ++h) g += (i >= pre[h]) ? 1 : 0;
     int j = i - pre[g];
-    const uint32_t w = te[2 * g + 1];
-    const uint8_t* rec = pool + 16ull * te[2 * g];
+    const uint32_t w = tel(2 * g + 1);
+    const uint8_t* rec = pool + 16ull * tel(2 * g);
     int xx, yy;
     T val;
     if (j < NS) {
