@@ -5,8 +5,8 @@ none of the compression method's arithmetic (no transform, threshold, encoding
 or stencil): everything here is a plain function of a NumPy ``default_rng``
 seed, so that both sides of a parity test start from the same bytes.
 
-Array convention: 2-D fields are indexed ``[y, x]`` (x fastest in memory), and
-multi-field states are ``[field, y, x]``.
+Array convention: 2-D fields are indexed ``[y, x]`` and 3-D fields ``[z, y, x]``
+(x fastest in memory); multi-field states put the field first.
 """
 from .fields import (
     fv_gaussians_and_step,
@@ -18,6 +18,7 @@ from .fields import (
     transport_gaussian,
     riemann_four_quadrants,
     shear_with_vortices,
+    taylor_green_jets_3d,
 )
 
 __all__ = [
@@ -30,4 +31,5 @@ __all__ = [
     "transport_gaussian",
     "riemann_four_quadrants",
     "shear_with_vortices",
+    "taylor_green_jets_3d",
 ]
