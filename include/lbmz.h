@@ -50,8 +50,10 @@ typedef enum {
 
 typedef enum { LBMZ_F32 = 0, LBMZ_F64 = 1 } lbmz_dtype;
 
-/* Periodic regular grid of n[0] x n[1] cells of size h (Section 1, the
- * periodicity condition).  dim must be 2; periodic must be 1; n[2] is ignored. */
+/* Periodic regular grid of n[0] x n[1] (x n[2]) cells of size h (Section 1,
+ * the periodicity condition).  dim is 2 (n[2] ignored) or 3 (the D3Q19
+ * scheme only, n[0] = n[1] = n[2]); periodic must be 1.  Dense fields are
+ * arrays [n[2]][n[1]][n[0]] (x fastest). */
 typedef struct {
   int dim;
   int64_t n[3];
@@ -75,7 +77,15 @@ typedef enum {
    * lambda = max(|u.N| + c) over both states, c = sqrt(gamma p / rho),
    * p = (gamma - 1)(E - rho |u|^2 / 2); time step dt = cfl * h / vel[0] with
    * vel[0] a bound of |u| + c given by the caller.  float32 only. */
-  LBMZ_EULER_RUSANOV = 2
+  LBMZ_EULER_RUSANOV = 2,
+  /* D3Q19 lattice-Boltzmann BGK on 3-D grids (the textbook scheme; the
+   * paper's subgrids of Section 3.1.1 are 3-D): 19 populations with
+   * velocities (0,0,0), (1,0,0) (-1,0,0) (0,1,0) (0,-1,0) (0,0,1) (0,0,-1),
+   * (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1)
+   * (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1), weights 1/3, 1/18, 1/36; pull
+   * streaming then collision with relaxation time tau; float32, folded BL5/3
+   * patches of 16^3 or 32^3 cells, float32 records only. */
+  LBMZ_LBM_D3Q19_BGK = 3
 } lbmz_scheme_kind;
 
 typedef struct {
@@ -117,8 +127,8 @@ typedef enum {
 } lbmz_values;
 
 /* Patch decomposition: p[0] = p[1] = cells per patch side, a power of two
- * in {8, 16, 32, 64} dividing n (32 or 64 for the narrow value formats).
- * p[2] is ignored. */
+ * in {8, 16, 32, 64} dividing n (32 or 64 for the narrow value formats);
+ * p[2] is ignored in 2-D and equals p[0] (16 or 32) in 3-D. */
 typedef struct {
   int p[3];
   lbmz_wavelet wavelet;
@@ -137,7 +147,8 @@ typedef struct {
   int32_t nfields;        /* 1 (FV), 9 (LBM) or 4 (Euler) */
   int32_t npatch;         /* patches in the grid */
   double totals[16];      /* FP64 per-field sums of the decompressed state: trapezoid
-                             weights 1/2 on shared bordering nodes (bl53), else 1 */
+                             weights 1/2 on shared bordering nodes (bl53), else 1;
+                             the first 16 fields (all of them: lbmz_get_totals) */
   int64_t regrows;        /* pool regrowths absorbed since creation */
   int64_t mask_records;   /* records stored as a bitmask */
   int64_t list_records;   /* records stored as an index list */
@@ -195,6 +206,14 @@ int lbmz_decompress_field(lbmz_ctx* ctx, int field, void* dst, size_t bytes, int
 
 int lbmz_stats(lbmz_ctx* ctx, lbmz_stats_t* out);
 
+/* The per-field totals of lbmz_stats for all `count` = nfields fields. */
+int lbmz_get_totals(lbmz_ctx* ctx, double* out, int count);
+
+/* D3Q19 only: set all populations to the equilibrium of the given density
+ * and velocity fields (each a dense n^3 float32 array [z][y][x]). */
+int lbmz_set_macroscopic3(lbmz_ctx* ctx, const void* rho, const void* ux, const void* uy, const void* uz,
+                          size_t bytes_each, int on_device);
+
 /* ---- compressed store access (checkpoint, parity tests) -------------------
  * Record order of the s x s coefficients of one (patch, field) tile, s = p + 1
  * (bl53) or p (Haar), in-place interleaved wavelet layout: the owned p x p
@@ -218,9 +237,12 @@ int lbmz_stats(lbmz_ctx* ctx, lbmz_stats_t* out);
  *   nearest even); zero pad to 8; then the u16 indices k of the kept details
  *   (when 2 ndet < 8 W) or W mask words over them; zero pad to 16.  The
  *   offset-table count is ndet, the number of kept details.
+ * 3-D tiles (D3Q19): s = p + 1 nodes per side; the record index of node
+ *   (x, y, z) is k = x + s y + s^2 z; W = ceil(s^3/64); float32 records
+ *   with the layout above.
  * Offset table: npatch * nfields entries of two u32, patch-major
- *   (patch index px + (n/p) py), field-minor: record offset in 16-byte units
- *   and the count | (1u << 31 when the record is a bitmask).
+ *   (patch index px + (n/p) py (+ (n/p)^2 pz)), field-minor: record offset
+ *   in 16-byte units and the count | (1u << 31 when the record is a bitmask).
  * Record placement in the pool is not canonical (any non-overlapping layout
  * is valid); the records themselves are. */
 
@@ -304,8 +326,8 @@ int lbmz_put_store(lbmz_ctx* ctx, const uint32_t* table_host, const void* pool_h
                    size_t pool_bytes);
 
 /* Replace the state by given wavelet coefficient tiles [npatch][nfields][s][s]
- * (dtype): the library thresholds and compacts them (the store's write path
- * fed with known coefficients). */
+ * ([npatch][19][s][s][s] in 3-D) (dtype): the library thresholds and
+ * compacts them (the store's write path fed with known coefficients). */
 int lbmz_set_coefficients(lbmz_ctx* ctx, const void* coef, size_t bytes, int on_device);
 
 const char* lbmz_last_error(const lbmz_ctx* ctx);

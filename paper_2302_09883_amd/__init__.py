@@ -8,6 +8,7 @@ from .lbmz import (  # noqa: F401
     LbmzError,
     Net,
     decode_records,
+    decode_records3,
     library,
     LIB_PATH,
 )

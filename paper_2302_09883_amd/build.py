@@ -28,6 +28,7 @@ SOURCES = [
     "lbmz_inst_f32_lbm_q.hip",
     "lbmz_inst_f32_euler.hip",
     "lbmz_net.hip",
+    "lbmz_d3q19.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,647 @@
+// Three-dimensional patch kernels for gfx950: D3Q19 BGK lattice Boltzmann on
+// cubic patches of 2^J cells, folded BL5/3 tiles of (2^J + 1)^3 nodes
+// (Section 3.1.1: shared bordering values, one ghost layer), tensor 3-D
+// transform (the 1-D transform along x on every line, then y, then z; the
+// inverse z, y, x), thresholds of Section 2.2 with one rank per dimension.
+//
+// A 33^3 tile of 19 float32 populations is 2.7 MB, far beyond the 160 KB of
+// LDS of a CU, so one step of a patch runs field by field through LDS (one
+// field tile, 143.7 KB at P = 32) with the populations staged in a per-
+// workgroup slice of global scratch:
+//   A  for every population i: expand its record into LDS (S1), inverse
+//      transform z, y, x (S2), and write the pull-streamed population
+//      f_i^in(n) = f_i(n - c_i) to scratch; values that come from outside
+//      the tile are read from the neighbours' exported halo (S3);
+//   B  BGK collision node by node in scratch (S4);
+//   C  for every population: load it into LDS, forward transform x, y, z
+//      (S5), hard threshold (S6), compaction into a record of the output pool
+//      (S7), inverse transform of the thresholded tile, FP64 trapezoid total
+//      (S9) and export of the planes and lines the neighbours pull from (S8).
+// The step kernel is persistent: one workgroup per scratch slice takes
+// patches from an atomic work queue until none is left.
+//
+// Record of one (patch, field): the kept coefficients in ascending flat tile
+// index t = x + S*y + S*S*z, then (8-byte aligned) the u16 indices t when
+// 2*nnz < 8*W, W = ceil(S^3 / 64), else W u64 mask words with bit t%64 of
+// word t/64 set for a kept coefficient; padded to 16 bytes.
+//
+// Halo of one patch (floats): six faces, face 2a + (sign > 0) holding, for
+// the five populations whose velocity has that sign along axis a (in
+// numbering order), the tile plane at coordinate P - 1 (positive sign) or 1
+// (negative sign), indexed u + S*v over the other two axes in increasing
+// order; then twelve edges, edge 4*pair + (c_a > 0) + 2*(c_b > 0) for the
+// axis pairs (x,y), (x,z), (y,z), holding the one population with that
+// velocity on the line at those two coordinates, indexed by the third axis.
+#include "lbmz_patch_kernel.h"
+
+namespace lbmz {
+
+struct D3Q19L {
+  static constexpr int C[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                                   {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                                   {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                   {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  // position of population i among the populations with the same velocity
+  // component along axis a (its slot in a halo face)
+  static constexpr int slot(int i, int a) {
+    int k = 0;
+    for (int j = 0; j < i; ++j) k += (C[j][a] == C[i][a]) ? 1 : 0;
+    return k;
+  }
+};
+
+template <int P_>
+struct Cfg3 {
+  static constexpr int P = P_;
+  static constexpr int S = P + 1;
+  static constexpr int S2 = S * S;
+  static constexpr int S3 = S * S * S;
+  static constexpr int M = 19;
+  static constexpr int NT = 1024;
+  static constexpr int NW = NT / 64;
+  static constexpr int W = (S3 + 63) / 64;
+  static constexpr int LMAX = ilog2c(P) - 1;
+  static constexpr int FACE = 5 * S2;
+  static constexpr int HALO = 6 * FACE + 12 * S;
+  static_assert(W <= NT, "one scan entry per thread");
+  static_assert(S3 < 65536, "u16 indices");
+};
+
+template <class C>
+struct Smem3 {
+  float tile[C::S3];
+  uint32_t pre[C::W];   // per-chunk counts, then their exclusive prefix
+  uint32_t wsum[C::NW];
+  double red[C::NW];
+  uint32_t misc[8];
+};
+
+// Exclusive prefix of a[0 .. n) in place (n <= NT); returns the total to all.
+template <class C, class SM>
+__device__ __forceinline__ uint32_t scan_counts(uint32_t* a, int n, SM& sm) {
+  const int t = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const uint32_t v = t < n ? a[t] : 0u;
+  const int incl = wave_incl_scan((int)v);
+  if (lane == 63) sm.wsum[wave] = (uint32_t)incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+  for (int w = 0; w < C::NW; ++w) {
+    const uint32_t s = sm.wsum[w];
+    off += (w < wave) ? s : 0u;
+    tot += s;
+  }
+  if (t < n) a[t] = off + (uint32_t)incl - v;
+  __syncthreads();
+  return tot;
+}
+
+// ---------------------------------------------------------------------------
+// Lines of the tile in registers: DIR 0 = x-lines, 1 = y-lines, 2 = z-lines.
+// ---------------------------------------------------------------------------
+template <class C, int DIR, bool FWD>
+__device__ __forceinline__ void line_pass(float* tile, int L) {
+  using LF = Lift<float, C::S, W_BL53, 1, C::LMAX>;
+  for (int l = threadIdx.x; l < C::S2; l += C::NT) {
+    int base, stride;
+    if constexpr (DIR == 0) {
+      base = l * C::S;
+      stride = 1;
+    } else if constexpr (DIR == 1) {
+      const int z = l / C::S;
+      base = (l - z * C::S) + z * C::S2;
+      stride = C::S;
+    } else {
+      base = l;
+      stride = C::S2;
+    }
+    float v[C::S];
+#pragma unroll
+    for (int k = 0; k < C::S; ++k) v[k] = tile[base + k * stride];
+    if constexpr (FWD) LF::fwd(v, L);
+    else LF::inv(v, L);
+#pragma unroll
+    for (int k = 0; k < C::S; ++k) tile[base + k * stride] = v[k];
+  }
+  __syncthreads();
+}
+
+template <class C>
+__device__ __forceinline__ void forward3(float* tile, int L) {
+  line_pass<C, 0, true>(tile, L);
+  line_pass<C, 1, true>(tile, L);
+  line_pass<C, 2, true>(tile, L);
+}
+
+template <class C>
+__device__ __forceinline__ void inverse3(float* tile, int L) {
+  line_pass<C, 2, false>(tile, L);
+  line_pass<C, 1, false>(tile, L);
+  line_pass<C, 0, false>(tile, L);
+}
+
+// ---------------------------------------------------------------------------
+// S1: record (patch q, field f) of the input store -> LDS tile
+// ---------------------------------------------------------------------------
+template <class C, class SM>
+__device__ void expand_field(const PatchArgs& a, int q, int f, SM& sm) {
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const size_t e = 2 * ((size_t)q * C::M + f);
+  const uint32_t off16 = a.table_in[e];
+  const uint32_t w = a.table_in[e + 1];
+  const uint32_t nnz = w & ~MASK_BIT;
+  const uint8_t* rec = a.pool_in + 16ull * off16;
+  const float* vals = reinterpret_cast<const float*>(rec);
+  const uint32_t vb = (4u * nnz + 7u) & ~7u;
+  if (w & MASK_BIT) {
+    const unsigned long long* words = reinterpret_cast<const unsigned long long*>(rec + vb);
+    if (tid < C::W) sm.pre[tid] = (uint32_t)__popcll(words[tid]);
+    __syncthreads();
+    scan_counts<C>(sm.pre, C::W, sm);
+    for (int c = wave; c < C::W; c += C::NW) {
+      const unsigned long long word = words[c];
+      const int t = 64 * c + lane;
+      const bool bit = ((word >> lane) & 1ull) != 0ull;
+      const float v = bit ? vals[sm.pre[c] + (uint32_t)__popcll(word & below(lane))] : 0.f;
+      if (t < C::S3) sm.tile[t] = v;
+    }
+  } else {
+    const uint16_t* idx = reinterpret_cast<const uint16_t*>(rec + vb);
+    zero_span<float>(sm.tile, C::S3, tid, C::NT);
+    __syncthreads();
+    for (int k = tid; k < (int)nnz; k += C::NT) sm.tile[idx[k]] = vals[k];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// S6 + S7: threshold the transformed tile in LDS and append its record to the
+// output pool.  Returns false when the pool is full (flag raised).
+// ---------------------------------------------------------------------------
+template <class C, class SM>
+__device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const int L = a.levels;
+  const float eps = (float)a.eps;
+  // S6: zero the dropped details (the inverse for the export needs them zero)
+  for (int t = tid; t < C::S3; t += C::NT) {
+    const int z = t / C::S2;
+    const int r = t - z * C::S2;
+    const int y = r / C::S;
+    const int x = r - y * C::S;
+    const int rx = dim_rank(x, L), ry = dim_rank(y, L), rz = dim_rank(z, L);
+    if (rx < 0 && ry < 0 && rz < 0) continue;   // pure sample: never zeroed
+    const int ax = rx < 0 ? 0 : rx, ay = ry < 0 ? 0 : ry, az = rz < 0 ? 0 : rz;
+    int rk = 0;
+    if (a.rule == R_CAPPED) rk = max(ax, max(ay, az));
+    else if (a.rule == R_ACCUM) rk = ax + ay + az;
+    const float thr = ldexpf(eps, rk);
+    const float c = sm.tile[t];
+    if (fabsf(c) < thr) sm.tile[t] = 0.f;
+  }
+  __syncthreads();
+  // S7: counts per 64-node chunk, prefix, one bump allocation per record
+  for (int c = wave; c < C::W; c += C::NW) {
+    const int t = 64 * c + lane;
+    const float v = t < C::S3 ? sm.tile[t] : 0.f;
+    const unsigned long long bits = __ballot(v != 0.f);
+    if (lane == 0) sm.pre[c] = (uint32_t)__popcll(bits);
+  }
+  __syncthreads();
+  const uint32_t nnz = scan_counts<C>(sm.pre, C::W, sm);
+  const bool ismask = !(2u * nnz < 8u * (uint32_t)C::W);
+  const uint32_t vb = (4u * nnz + 7u) & ~7u;
+  const uint32_t mb = ismask ? 8u * (uint32_t)C::W : 2u * nnz;
+  const uint32_t rb16 = (vb + mb + 15u) / 16u;
+  if (tid == 0) {
+    const unsigned long long base = atomicAdd(&a.ctrl->top16[a.epoch % 3u], (unsigned long long)rb16);
+    const bool ok = base + rb16 <= a.cap16;
+    if (!ok) {
+      atomicOr(&a.ctrl->abort, ABORT_OVERFLOW);
+      atomicMin(&a.ctrl->abort_epoch, a.epoch);
+    } else {
+      const size_t e = 2 * ((size_t)q * C::M + f);
+      a.table_out[e] = (uint32_t)base;
+      a.table_out[e + 1] = nnz | (ismask ? MASK_BIT : 0u);
+    }
+    sm.misc[0] = ok ? 1u : 0u;
+    sm.misc[1] = (uint32_t)base;
+  }
+  __syncthreads();
+  if (!sm.misc[0]) return false;
+  uint8_t* rec = a.pool_out + 16ull * sm.misc[1];
+  float* vals = reinterpret_cast<float*>(rec);
+  uint16_t* idx = reinterpret_cast<uint16_t*>(rec + vb);
+  unsigned long long* words = reinterpret_cast<unsigned long long*>(rec + vb);
+  for (int c = wave; c < C::W; c += C::NW) {
+    const int t = 64 * c + lane;
+    const float v = t < C::S3 ? sm.tile[t] : 0.f;
+    const unsigned long long bits = __ballot(v != 0.f);
+    const uint32_t k = sm.pre[c] + (uint32_t)__popcll(bits & below(lane));
+    if (v != 0.f) {
+      vals[k] = v;
+      if (!ismask) idx[k] = (uint16_t)t;
+    }
+    if (ismask && lane == 0) words[c] = bits;
+  }
+  // zero padding: after the values, and from the end of the indices or
+  // words to the end of the record
+  if (tid == 0 && (nnz & 1u)) vals[nnz] = 0.f;
+  const uint32_t tail0 = (vb + mb) / 2u, tail1 = rb16 * 8u;
+  uint16_t* h = reinterpret_cast<uint16_t*>(rec);
+  if (tid < (int)(tail1 - tail0)) h[tail0 + tid] = 0;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// S9: FP64 trapezoid total of the reconstructed tile (1/2 per shared
+// bordering node and dimension); a non-finite total raises the abort flag.
+// ---------------------------------------------------------------------------
+template <class C, bool CHECK, class SM>
+__device__ void total_field(const PatchArgs& a, int q, int f, SM& sm) {
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int t = tid; t < C::S3; t += C::NT) {
+    const int z = t / C::S2;
+    const int r = t - z * C::S2;
+    const int y = r / C::S;
+    const int x = r - y * C::S;
+    const int nb = (x == 0 || x == C::P) + (y == 0 || y == C::P) + (z == 0 || z == C::P);
+    part += ldexp((double)sm.tile[t], -nb);
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) part += __shfl_down(part, d, 64);
+  if (lane_id() == 0) sm.red[wave_id()] = part;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < C::NW; ++w) s += sm.red[w];
+    a.partials_out[(size_t)q * C::M + f] = s;
+    if (CHECK && !(fabs(s) <= 0x1.fffffffffffffp+1023)) {
+      atomicOr(&a.ctrl->abort, ABORT_NONFINITE);
+      atomicMin(&a.ctrl->abort_epoch, a.epoch);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S8: export of population f's planes and line for the neighbours
+// ---------------------------------------------------------------------------
+template <class C, class SM>
+__device__ void export_field(const PatchArgs& a, int q, int f, SM& sm) {
+  if (f == 0) return;
+  const int tid = threadIdx.x;
+  float* h = static_cast<float*>(a.halo_out) + (size_t)q * C::HALO;
+  int cc[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cc[d] = 0;
+  // population f's velocity (f is wave-uniform; a small constant table walk)
+#pragma unroll
+  for (int i = 1; i < C::M; ++i)
+    if (i == f) {
+      cc[0] = D3Q19L::C[i][0];
+      cc[1] = D3Q19L::C[i][1];
+      cc[2] = D3Q19L::C[i][2];
+    }
+  int slots[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 1; i < C::M; ++i)
+    if (i == f) {
+      slots[0] = D3Q19L::slot(i, 0);
+      slots[1] = D3Q19L::slot(i, 1);
+      slots[2] = D3Q19L::slot(i, 2);
+    }
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (cc[ax] == 0) continue;
+    const int k = cc[ax] > 0 ? C::P - 1 : 1;
+    // strides of the plane's own axis and of its (u, v) axes in increasing order
+    const int s_ax = ax == 0 ? 1 : (ax == 1 ? C::S : C::S2);
+    const int s_u = ax == 0 ? C::S : 1;
+    const int s_v = ax == 2 ? C::S : C::S2;
+    float* dst = h + (size_t)(2 * ax + (cc[ax] > 0 ? 1 : 0)) * C::FACE + (size_t)slots[ax] * C::S2;
+    for (int i = tid; i < C::S2; i += C::NT) {
+      const int v = i / C::S;
+      const int u = i - v * C::S;
+      dst[i] = sm.tile[k * s_ax + u * s_u + v * s_v];
+    }
+  }
+  const int nz = (cc[0] != 0) + (cc[1] != 0) + (cc[2] != 0);
+  if (nz == 2 && tid < C::S) {
+    // axis pair (x,y), (x,z) or (y,z) with non-zero components, and the third axis
+    const int pr = cc[2] == 0 ? 0 : (cc[1] == 0 ? 1 : 2);
+    const int ca = pr == 2 ? cc[1] : cc[0];
+    const int cb = pr == 0 ? cc[1] : cc[2];
+    const int sa = pr == 2 ? C::S : 1;
+    const int sb = pr == 0 ? C::S : C::S2;
+    const int sw = pr == 0 ? C::S2 : (pr == 1 ? C::S : 1);
+    const int e = 4 * pr + (ca > 0 ? 1 : 0) + 2 * (cb > 0 ? 1 : 0);
+    const int ka = ca > 0 ? C::P - 1 : 1;
+    const int kb = cb > 0 ? C::P - 1 : 1;
+    h[6 * (size_t)C::FACE + (size_t)e * C::S + tid] = sm.tile[ka * sa + kb * sb + tid * sw];
+  }
+}
+
+// Value of population f pulled from (mx, my, mz), a node off the tile in one
+// or two dimensions, out of the halo exported by the neighbour owning it.
+template <class C>
+__device__ __forceinline__ float halo_value(const PatchArgs& a, int q, const int* cf, const int* sl, int mx, int my,
+                                            int mz) {
+  const int ox = mx < 0 ? -1 : (mx >= C::S ? 1 : 0);
+  const int oy = my < 0 ? -1 : (my >= C::S ? 1 : 0);
+  const int oz = mz < 0 ? -1 : (mz >= C::S ? 1 : 0);
+  const int npx = a.npx;
+  const int pz = q / (npx * npx);
+  const int py = (q / npx) % npx;
+  const int px = q % npx;
+  const int qn = (px + ox + npx) % npx + npx * ((py + oy + npx) % npx) + npx * npx * ((pz + oz + npx) % npx);
+  const float* h = static_cast<const float*>(a.halo_in) + (size_t)qn * C::HALO;
+  const int nout = (ox != 0) + (oy != 0) + (oz != 0);
+  if (nout == 1) {
+    // a face: axis ax, the other two coordinates (u, v) in increasing axis order
+    const int ax = ox ? 0 : (oy ? 1 : 2);
+    const int u = ax == 0 ? my : mx;
+    const int v = ax == 2 ? my : mz;
+    const int c = ax == 0 ? cf[0] : (ax == 1 ? cf[1] : cf[2]);
+    const int k = ax == 0 ? sl[0] : (ax == 1 ? sl[1] : sl[2]);
+    return h[(size_t)(2 * ax + (c > 0 ? 1 : 0)) * C::FACE + (size_t)k * C::S2 + u + C::S * v];
+  }
+  // an edge: the axis pair off the tile and the coordinate along the third axis
+  const int pr = oz == 0 ? 0 : (oy == 0 ? 1 : 2);
+  const int ca = pr == 2 ? cf[1] : cf[0];
+  const int cb = pr == 0 ? cf[1] : cf[2];
+  const int w = pr == 0 ? mz : (pr == 1 ? my : mx);
+  const int e = 4 * pr + (ca > 0 ? 1 : 0) + 2 * (cb > 0 ? 1 : 0);
+  return h[6 * (size_t)C::FACE + (size_t)e * C::S + w];
+}
+
+// S3 + streaming: f^in_f(n) = f_f(n - c_f) into scratch, from the LDS tile or
+// the neighbours' halo.
+template <class C, class SM>
+__device__ void stream_field(const PatchArgs& a, int q, int f, float* scr, SM& sm) {
+  int cf[3] = {0, 0, 0}, sl[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 1; i < C::M; ++i)
+    if (i == f) {
+      cf[0] = D3Q19L::C[i][0];
+      cf[1] = D3Q19L::C[i][1];
+      cf[2] = D3Q19L::C[i][2];
+      sl[0] = D3Q19L::slot(i, 0);
+      sl[1] = D3Q19L::slot(i, 1);
+      sl[2] = D3Q19L::slot(i, 2);
+    }
+  const int shift = cf[0] + C::S * cf[1] + C::S2 * cf[2];
+  float* dst = scr + (size_t)f * C::S3;
+  for (int t = threadIdx.x; t < C::S3; t += C::NT) {
+    const int z = t / C::S2;
+    const int r = t - z * C::S2;
+    const int y = r / C::S;
+    const int x = r - y * C::S;
+    const int mx = x - cf[0], my = y - cf[1], mz = z - cf[2];
+    const bool in = (unsigned)mx < (unsigned)C::S && (unsigned)my < (unsigned)C::S && (unsigned)mz < (unsigned)C::S;
+    dst[t] = in ? sm.tile[t - shift] : halo_value<C>(a, q, cf, sl, mx, my, mz);
+  }
+}
+
+// S4: BGK collision of every node of the patch in scratch (in place).
+template <class C>
+__device__ void collide(const PatchArgs& a, float* scr) {
+  const float om = (float)a.omega;
+  for (int t = threadIdx.x; t < C::S3; t += C::NT) {
+    float fi[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) fi[i] = scr[(size_t)i * C::S3 + t];
+    float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      rho += fi[i];
+      if (D3Q19L::C[i][0]) jx += D3Q19L::C[i][0] > 0 ? fi[i] : -fi[i];
+      if (D3Q19L::C[i][1]) jy += D3Q19L::C[i][1] > 0 ? fi[i] : -fi[i];
+      if (D3Q19L::C[i][2]) jz += D3Q19L::C[i][2] > 0 ? fi[i] : -fi[i];
+    }
+    const float ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    const float usq = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const float w = i == 0 ? (1.f / 3.f) : (i < 7 ? (1.f / 18.f) : (1.f / 36.f));
+      const float cu = (float)D3Q19L::C[i][0] * ux + (float)D3Q19L::C[i][1] * uy + (float)D3Q19L::C[i][2] * uz;
+      const float feq = w * rho * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * usq);
+      scr[(size_t)i * C::S3 + t] = fi[i] - om * (fi[i] - feq);
+    }
+  }
+}
+
+// C: from a transformed-or-not tile in LDS to the record, totals and export.
+template <class C, class SM>
+__device__ void finish_field(const PatchArgs& a, int q, int f, SM& sm) {
+  compact_field<C>(a, q, f, sm);
+  __syncthreads();   // the record stores read the tile
+  inverse3<C>(sm.tile, a.levels);
+  total_field<C, true>(a, q, f, sm);
+  export_field<C>(a, q, f, sm);
+  __syncthreads();
+}
+
+template <class C, class SM>
+__device__ void step_patch(const PatchArgs& a, int q, float* scr, SM& sm) {
+  const int L = a.levels;
+  for (int f = 0; f < C::M; ++f) {
+    expand_field<C>(a, q, f, sm);
+    inverse3<C>(sm.tile, L);
+    stream_field<C>(a, q, f, scr, sm);
+    __syncthreads();
+  }
+  collide<C>(a, scr);
+  __syncthreads();
+  for (int f = 0; f < C::M; ++f) {
+    const float* src = scr + (size_t)f * C::S3;
+    for (int t = threadIdx.x; t < C::S3; t += C::NT) sm.tile[t] = src[t];
+    __syncthreads();
+    forward3<C>(sm.tile, L);
+    finish_field<C>(a, q, f, sm);
+  }
+}
+
+// One step of every patch: persistent workgroups, each with its own scratch
+// slice (blockIdx.x), take patches from the work queue of this epoch.
+template <int P>
+__global__ __launch_bounds__(1024) void d3q19_step_kernel(PatchArgs a) {
+  using C = Cfg3<P>;
+  __shared__ Smem3<C> sm;
+  if (step_stops(a, blockIdx.x == 0, sm)) return;
+  float* scr = a.scratch + (size_t)blockIdx.x * C::M * C::S3;
+  for (;;) {
+    if (threadIdx.x == 0) sm.misc[3] = atomicAdd(&a.ctrl->queue[a.epoch % 3u], 1u);
+    __syncthreads();
+    const int q = (int)sm.misc[3];
+    __syncthreads();
+    if (q >= a.npatch) break;
+    step_patch<C>(a, q, scr, sm);
+  }
+}
+
+// Auxiliary modes, one workgroup per patch.
+template <int P>
+__global__ __launch_bounds__(1024) void d3q19_aux_kernel(PatchArgs a) {
+  using C = Cfg3<P>;
+  __shared__ Smem3<C> sm;
+  const int q = blockIdx.x;
+  const int n = a.n;
+  const int npx = a.npx;
+  const int pz = q / (npx * npx), py = (q / npx) % npx, px = q % npx;
+  for (int f = 0; f < C::M; ++f) {
+    if (a.mode == AUX_INIT) {
+      const float* src = static_cast<const float*>(a.dense_in) + (size_t)f * n * n * n;
+      for (int t = threadIdx.x; t < C::S3; t += C::NT) {
+        const int z = t / C::S2;
+        const int r = t - z * C::S2;
+        const int y = r / C::S;
+        const int x = r - y * C::S;
+        const int gx = (px * C::P + x) % n, gy = (py * C::P + y) % n, gz = (pz * C::P + z) % n;
+        sm.tile[t] = src[((size_t)gz * n + gy) * n + gx];
+      }
+      __syncthreads();
+      forward3<C>(sm.tile, a.levels);
+      finish_field<C>(a, q, f, sm);
+    } else if (a.mode == AUX_COEF) {
+      const float* src = static_cast<const float*>(a.coef_in) + ((size_t)q * C::M + f) * C::S3;
+      for (int t = threadIdx.x; t < C::S3; t += C::NT) sm.tile[t] = src[t];
+      __syncthreads();
+      finish_field<C>(a, q, f, sm);
+    } else {
+      expand_field<C>(a, q, f, sm);
+      inverse3<C>(sm.tile, a.levels);
+      if (a.mode == AUX_RESTORE) {
+        total_field<C, false>(a, q, f, sm);
+        export_field<C>(a, q, f, sm);
+      } else {
+        float* dst = static_cast<float*>(a.dense_out) + (size_t)f * n * n * n;
+        for (int t = threadIdx.x; t < C::P * C::P * C::P; t += C::NT) {
+          const int z = t / (C::P * C::P);
+          const int r = t - z * C::P * C::P;
+          const int y = r / C::P;
+          const int x = r - y * C::P;
+          dst[((size_t)(pz * C::P + z) * n + (py * C::P + y)) * n + (px * C::P + x)] =
+              sm.tile[x + C::S * y + C::S2 * z];
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Uncompressed D3Q19 BGK step on a periodic [19][n][n][n] grid.
+__global__ void d3q19_ref_kernel(const float* __restrict__ in, float* __restrict__ out, int n, float om) {
+  const size_t nn = (size_t)n * n * n;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nn) return;
+  const int x = (int)(t % n);
+  const int y = (int)((t / n) % n);
+  const int z = (int)(t / ((size_t)n * n));
+  float fi[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int sx = (x - D3Q19L::C[i][0] + n) % n;
+    const int sy = (y - D3Q19L::C[i][1] + n) % n;
+    const int sz = (z - D3Q19L::C[i][2] + n) % n;
+    fi[i] = in[(size_t)i * nn + ((size_t)sz * n + sy) * n + sx];
+  }
+  float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    rho += fi[i];
+    if (D3Q19L::C[i][0]) jx += D3Q19L::C[i][0] > 0 ? fi[i] : -fi[i];
+    if (D3Q19L::C[i][1]) jy += D3Q19L::C[i][1] > 0 ? fi[i] : -fi[i];
+    if (D3Q19L::C[i][2]) jz += D3Q19L::C[i][2] > 0 ? fi[i] : -fi[i];
+  }
+  const float ux = jx / rho, uy = jy / rho, uz = jz / rho;
+  const float usq = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const float w = i == 0 ? (1.f / 3.f) : (i < 7 ? (1.f / 18.f) : (1.f / 36.f));
+    const float cu = (float)D3Q19L::C[i][0] * ux + (float)D3Q19L::C[i][1] * uy + (float)D3Q19L::C[i][2] * uz;
+    const float feq = w * rho * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * usq);
+    out[(size_t)i * nn + t] = fi[i] - om * (fi[i] - feq);
+  }
+}
+
+// Equilibrium populations [19][n^3] from rho, ux, uy, uz [n^3].
+__global__ void d3q19_equilibrium_kernel(const float* rho, const float* ux, const float* uy, const float* uz,
+                                         float* f, size_t nn) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nn) return;
+  const float r = rho[t], u = ux[t], v = uy[t], w3 = uz[t];
+  const float usq = u * u + v * v + w3 * w3;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const float w = i == 0 ? (1.f / 3.f) : (i < 7 ? (1.f / 18.f) : (1.f / 36.f));
+    const float cu = (float)D3Q19L::C[i][0] * u + (float)D3Q19L::C[i][1] * v + (float)D3Q19L::C[i][2] * w3;
+    f[(size_t)i * nn + t] = w * r * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * usq);
+  }
+}
+
+hipError_t launch_reference_step3(const void* in, void* out, int n, double omega, hipStream_t s) {
+  const size_t nn = (size_t)n * n * n;
+  hipLaunchKernelGGL(d3q19_ref_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const float*>(in), static_cast<float*>(out), n, (float)omega);
+  return hipGetLastError();
+}
+
+hipError_t launch_equilibrium3(const void* rho, const void* ux, const void* uy, const void* uz, void* f, int n,
+                               hipStream_t s) {
+  const size_t nn = (size_t)n * n * n;
+  hipLaunchKernelGGL(d3q19_equilibrium_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const float*>(rho), static_cast<const float*>(ux), static_cast<const float*>(uy),
+                     static_cast<const float*>(uz), static_cast<float*>(f), nn);
+  return hipGetLastError();
+}
+
+template <int P>
+static void d3q19_case(int op, const PatchArgs* a, int grid, hipStream_t s, hipError_t* err, size_t* out) {
+  using C = Cfg3<P>;
+  switch (op) {
+    case 0:   // step (plain launch and persistent launch are the same kernel)
+    case 3:
+      hipLaunchKernelGGL(d3q19_step_kernel<P>, dim3((unsigned)grid), dim3(C::NT), 0, s, *a);
+      *err = hipGetLastError();
+      break;
+    case 1:
+      hipLaunchKernelGGL(d3q19_aux_kernel<P>, dim3((unsigned)grid), dim3(C::NT), 0, s, *a);
+      *err = hipGetLastError();
+      break;
+    case 2:
+      *out = sizeof(Smem3<C>);
+      break;
+    case 4:
+    case 5:
+      *out = reinterpret_cast<size_t>(reinterpret_cast<const void*>(&d3q19_step_kernel<P>));
+      break;
+    case 6:
+      *out = (size_t)C::NT;
+      break;
+    case 7:   // halo floats per patch
+      *out = (size_t)C::HALO;
+      break;
+    case 8:   // scratch floats per workgroup
+      *out = (size_t)C::M * C::S3;
+      break;
+    default:
+      *err = hipErrorInvalidValue;
+  }
+}
+
+bool dispatch_f32_d3q19(LBMZ_DISPATCH_ARGS) {
+  if (k.dtype != 0 || k.scheme != S_LBM3 || k.wavelet != W_BL53 || k.vf != VF_F32) return false;
+  switch (k.p) {
+    case 16: d3q19_case<16>(op, a, grid, s, err, out); return true;
+    case 32: d3q19_case<32>(op, a, grid, s, err, out); return true;
+    default: return false;
+  }
+}
+
+}  // namespace lbmz

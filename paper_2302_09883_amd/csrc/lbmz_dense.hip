@@ -152,9 +152,9 @@ hipError_t launch_equilibrium(int dtype, const void* rho, const void* ux, const 
   return hipGetLastError();
 }
 
-hipError_t launch_dense_totals(int dtype, const void* in, int nfields, int n, double* partials, int nblocks,
+hipError_t launch_dense_totals(int dtype, const void* in, int nfields, size_t cells, double* partials, int nblocks,
                                hipStream_t s) {
-  const size_t nn = (size_t)n * n;
+  const size_t nn = cells;
   const dim3 grid((unsigned)nblocks, (unsigned)nfields);
   if (dtype == 0)
     hipLaunchKernelGGL(dense_sum_kernel<float>, grid, dim3(256), 0, s, static_cast<const float*>(in), nfields,

@@ -7,7 +7,7 @@
 namespace lbmz {
 
 enum Wavelet : int { W_HAAR = 0, W_BL53 = 1 };
-enum SchemeKind : int { S_FV = 0, S_LBM = 1, S_EULER = 2 };
+enum SchemeKind : int { S_FV = 0, S_LBM = 1, S_EULER = 2, S_LBM3 = 3 };   // S_LBM3: D3Q19 on 3-D grids
 enum Rule : int { R_CAPPED = 0, R_CONSTANT = 1, R_ACCUM = 2 };
 // How the values of a record are stored: float32 (every kept coefficient), or
 // float32 samples plus binary16 / OCP E4M3 details with per-subband scales.
@@ -59,14 +59,15 @@ struct PatchArgs {
   uint32_t* table_out;
   void* halo_out;
   double* partials_out;          // [npatch][nfields]
+  float* scratch;                // 3-D step: per-workgroup population staging [grid][19][S^3]
   unsigned long long cap16;      // pool_out capacity in 16-byte units
   Ctrl* ctrl;
   unsigned int epoch;            // launch counter
   // auxiliary modes
   int mode;
-  const void* dense_in;          // AUX_INIT: [nfields][n][n]
-  const void* coef_in;           // AUX_COEF: [npatch][nfields][s][s]
-  void* dense_out;               // AUX_DECOMP: [nfields][n][n]
+  const void* dense_in;          // AUX_INIT: [nfields][n][n] ([nfields][n][n][n] in 3-D)
+  const void* coef_in;           // AUX_COEF: [npatch][nfields][s][s] ([...][s][s][s] in 3-D)
+  void* dense_out;               // AUX_DECOMP: same layout as dense_in
 };
 
 // Configuration key of a compiled kernel family.
@@ -102,9 +103,14 @@ hipError_t launch_reference_step(int dtype, int scheme, const void* in, void* ou
 // D2Q9 equilibrium populations [9][n][n] from rho, ux, uy [n][n].
 hipError_t launch_equilibrium(int dtype, const void* rho, const void* ux, const void* uy,
                               void* f, int n, hipStream_t s);
-// Per-field trapezoid-free sums of a dense state into totals [nfields] (FP64,
-// fixed reduction order), for the reference context.
-hipError_t launch_dense_totals(int dtype, const void* in, int nfields, int n, double* partials,
+// Per-field trapezoid-free sums of a dense state of `cells` nodes per field
+// into partials [nfields][nblocks] (FP64, fixed reduction order), for the
+// reference context.
+hipError_t launch_dense_totals(int dtype, const void* in, int nfields, size_t cells, double* partials,
                                int nblocks, hipStream_t s);
+// D3Q19 (float32, periodic [19][n][n][n]): uncompressed step and equilibrium.
+hipError_t launch_reference_step3(const void* in, void* out, int n, double omega, hipStream_t s);
+hipError_t launch_equilibrium3(const void* rho, const void* ux, const void* uy, const void* uz, void* f, int n,
+                               hipStream_t s);
 
 }  // namespace lbmz

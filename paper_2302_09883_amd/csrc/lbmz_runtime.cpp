@@ -29,12 +29,13 @@ bool dispatch_f64_lbm(LBMZ_DISPATCH_ARGS);
 bool dispatch_f32_fv_q(LBMZ_DISPATCH_ARGS);
 bool dispatch_f32_lbm_q(LBMZ_DISPATCH_ARGS);
 bool dispatch_f32_euler(LBMZ_DISPATCH_ARGS);
+bool dispatch_f32_d3q19(LBMZ_DISPATCH_ARGS);
 
 static bool dispatch(LBMZ_DISPATCH_ARGS) {
   return dispatch_f32_fv(k, op, a, grid, s, err, out) || dispatch_f32_lbm(k, op, a, grid, s, err, out) ||
          dispatch_f64_fv(k, op, a, grid, s, err, out) || dispatch_f64_lbm(k, op, a, grid, s, err, out) ||
          dispatch_f32_fv_q(k, op, a, grid, s, err, out) || dispatch_f32_lbm_q(k, op, a, grid, s, err, out) ||
-         dispatch_f32_euler(k, op, a, grid, s, err, out);
+         dispatch_f32_euler(k, op, a, grid, s, err, out) || dispatch_f32_d3q19(k, op, a, grid, s, err, out);
 }
 
 static size_t dispatch_op_of(const KernelKey& k, int op, const PatchArgs* a, int grid, hipStream_t s,
@@ -81,6 +82,13 @@ int kernel_threads(const KernelKey& k) {
 }
 
 bool have_kernel(const KernelKey& k) { return kernel_lds_bytes(k) != 0; }
+
+// 3-D kernels: halo floats per patch and scratch floats per workgroup.
+static size_t kernel_size_op(const KernelKey& k, int op) {
+  hipError_t e = hipSuccess;
+  const size_t v = dispatch_op_of(k, op, nullptr, 0, nullptr, &e);
+  return e == hipSuccess ? v : 0;
+}
 }  // namespace lbmz
 
 using namespace lbmz;
@@ -90,6 +98,9 @@ struct lbmz_ctx {
   int dtype = 0;
   size_t esize = 4;
   int n = 0, p = 0, npx = 0, npatch = 0, s = 0, levels = 0, wavelet = 0, rule = 0, scheme = 0;
+  int dim = 2;
+  float* scratch = nullptr;   // 3-D step: per-workgroup population staging
+  int slots3 = 0;             // 3-D step: resident workgroups (scratch slices)
   int vf = VF_F32;   // ValueFormat of the records
   // execution of the step: persistent work-queue kernel, hipGraph chunks
   int exec_persistent = 0, exec_graph = 0, persist_grid = 0;
@@ -152,7 +163,7 @@ int fail(lbmz_ctx* c, int code, const char* fmt, ...) {
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
-int64_t ncoef(const lbmz_ctx* c) { return (int64_t)c->s * c->s; }
+int64_t ncoef(const lbmz_ctx* c) { return (int64_t)c->s * c->s * (c->dim == 3 ? c->s : 1); }
 int64_t nwords(const lbmz_ctx* c) { return (ncoef(c) + 63) / 64; }
 
 // Record bytes for nnz stored coefficients (layout of include/lbmz.h).
@@ -208,8 +219,13 @@ void dfree(lbmz_ctx* c, void* p) {
   else (void)hipFree(p);
 }
 
-size_t dense_bytes(const lbmz_ctx* c) { return (size_t)c->n * c->n * c->nfields * c->esize; }
-size_t field_bytes(const lbmz_ctx* c) { return (size_t)c->n * c->n * c->esize; }
+size_t cells(const lbmz_ctx* c) { return (size_t)c->n * c->n * (c->dim == 3 ? (size_t)c->n : 1); }
+size_t dense_bytes(const lbmz_ctx* c) { return cells(c) * c->nfields * c->esize; }
+size_t field_bytes(const lbmz_ctx* c) { return cells(c) * c->esize; }
+size_t halo_bytes(const lbmz_ctx* c) {
+  if (c->dim == 3) return sizeof(float) * kernel_size_op(c->key, 7) * (size_t)c->npatch;
+  return c->esize * 4 * (size_t)c->nslot * c->s * c->npatch;
+}
 
 int ensure_buffers(lbmz_ctx* c) {
   if (c->allocated) return LBMZ_OK;
@@ -225,7 +241,7 @@ int ensure_buffers(lbmz_ctx* c) {
   } else {
     if (c->cap_bytes <= 0) c->cap_bytes = align_up(std::max<int64_t>(worst_store_bytes(c) / 4, 4096), 256);
     const size_t tb = sizeof(uint32_t) * 2 * (size_t)c->npatch * c->nfields;
-    const size_t hb = c->esize * 4 * (size_t)c->nslot * c->s * c->npatch;
+    const size_t hb = halo_bytes(c);
     const size_t pb = sizeof(double) * (size_t)c->npatch * c->nfields;
     for (int b = 0; b < 2; ++b) {
       c->pool[b] = static_cast<uint8_t*>(dalloc(c, (size_t)c->cap_bytes));
@@ -237,6 +253,11 @@ int ensure_buffers(lbmz_ctx* c) {
       HIPCHK(c, hipMemsetAsync(c->table[b], 0, tb, c->stream));
       HIPCHK(c, hipMemsetAsync(c->halo[b], 0, hb, c->stream));
       HIPCHK(c, hipMemsetAsync(c->partials[b], 0, pb, c->stream));
+    }
+    if (c->dim == 3) {
+      const size_t sb = sizeof(float) * kernel_size_op(c->key, 8) * (size_t)c->slots3;
+      c->scratch = static_cast<float*>(dalloc(c, sb));
+      if (!c->scratch) return fail(c, LBMZ_ENOMEM, "step scratch allocation failed");
     }
     c->ctrl = static_cast<Ctrl*>(dalloc(c, sizeof(Ctrl)));
     if (!c->ctrl) return fail(c, LBMZ_ENOMEM, "control block allocation failed");
@@ -306,6 +327,7 @@ PatchArgs args_for(lbmz_ctx* c, int in, int out, unsigned epoch) {
   a.epoch = epoch;
   a.eps_patch = c->eps_patch;
   a.features = c->features;
+  a.scratch = c->scratch;
   return a;
 }
 
@@ -384,16 +406,24 @@ int copy_in(lbmz_ctx* c, void* dst, const void* src, size_t bytes, int on_device
 
 int validate_common(const lbmz_grid* g, const lbmz_scheme* sc, lbmz_ctx* c) {
   if (!g || !sc) return fail(c, LBMZ_EINVAL, "null argument");
-  if (g->dim != 2) return fail(c, LBMZ_EINVAL, "only 2-D grids are supported (dim=%d)", g->dim);
+  if (g->dim != 2 && g->dim != 3) return fail(c, LBMZ_EINVAL, "grids are 2-D or 3-D (dim=%d)", g->dim);
   if (!g->periodic) return fail(c, LBMZ_EINVAL, "only periodic grids are supported");
-  if (g->n[0] <= 0 || g->n[0] != g->n[1] || g->n[0] > (1 << 16))
-    return fail(c, LBMZ_EINVAL, "grid must be square with 0 < n <= 65536");
+  if (g->dim == 3) {
+    if (sc->kind != LBMZ_LBM_D3Q19_BGK) return fail(c, LBMZ_EINVAL, "3-D grids run the D3Q19 scheme only");
+    if (g->n[0] <= 0 || g->n[0] != g->n[1] || g->n[0] != g->n[2] || g->n[0] > 2048)
+      return fail(c, LBMZ_EINVAL, "3-D grid must be cubic with 0 < n <= 2048");
+    if (sc->dtype != LBMZ_F32) return fail(c, LBMZ_EINVAL, "the D3Q19 scheme is float32");
+  } else {
+    if (sc->kind == LBMZ_LBM_D3Q19_BGK) return fail(c, LBMZ_EINVAL, "the D3Q19 scheme needs a 3-D grid");
+    if (g->n[0] <= 0 || g->n[0] != g->n[1] || g->n[0] > (1 << 16))
+      return fail(c, LBMZ_EINVAL, "grid must be square with 0 < n <= 65536");
+  }
   if (sc->dtype != LBMZ_F32 && sc->dtype != LBMZ_F64) return fail(c, LBMZ_EINVAL, "bad dtype");
   if (sc->kind == LBMZ_FV_UPWIND) {
     const double vmax = std::max(std::fabs(sc->vel[0]), std::fabs(sc->vel[1]));
     if (!(vmax > 0.0) || !std::isfinite(vmax)) return fail(c, LBMZ_EINVAL, "FV velocity must be non-zero");
     if (!(sc->cfl > 0.0) || !std::isfinite(sc->cfl)) return fail(c, LBMZ_EINVAL, "cfl must be > 0");
-  } else if (sc->kind == LBMZ_LBM_D2Q9_BGK) {
+  } else if (sc->kind == LBMZ_LBM_D2Q9_BGK || sc->kind == LBMZ_LBM_D3Q19_BGK) {
     if (!(sc->tau > 0.5) || !std::isfinite(sc->tau)) return fail(c, LBMZ_EINVAL, "tau must be > 1/2");
   } else if (sc->kind == LBMZ_EULER_RUSANOV) {
     if (!(sc->vel[0] > 0.0) || !std::isfinite(sc->vel[0]))
@@ -404,10 +434,14 @@ int validate_common(const lbmz_grid* g, const lbmz_scheme* sc, lbmz_ctx* c) {
     return fail(c, LBMZ_EINVAL, "unknown scheme kind %d", (int)sc->kind);
   }
   c->n = (int)g->n[0];
+  c->dim = g->dim;
   c->dtype = sc->dtype == LBMZ_F64 ? 1 : 0;
   c->esize = c->dtype ? 8 : 4;
-  c->scheme = sc->kind == LBMZ_LBM_D2Q9_BGK ? S_LBM : (sc->kind == LBMZ_EULER_RUSANOV ? S_EULER : S_FV);
-  c->nfields = c->scheme == S_LBM ? 9 : (c->scheme == S_EULER ? 4 : 1);
+  c->scheme = sc->kind == LBMZ_LBM_D2Q9_BGK ? S_LBM
+              : sc->kind == LBMZ_EULER_RUSANOV ? S_EULER
+              : sc->kind == LBMZ_LBM_D3Q19_BGK ? S_LBM3
+                                               : S_FV;
+  c->nfields = c->scheme == S_LBM ? 9 : (c->scheme == S_EULER ? 4 : (c->scheme == S_LBM3 ? 19 : 1));
   c->nslot = c->scheme == S_LBM ? 3 : c->nfields;
   PatchArgs& a = c->base;
   memset(&a, 0, sizeof a);
@@ -442,7 +476,10 @@ void drop_graphs(lbmz_ctx* c) {
   }
 }
 
-int step_grid(lbmz_ctx* c) { return c->exec_persistent ? c->persist_grid : c->npatch; }
+int step_grid(lbmz_ctx* c) {
+  if (c->dim == 3) return c->slots3;   // the 3-D step kernel is always persistent
+  return c->exec_persistent ? c->persist_grid : c->npatch;
+}
 
 // Arguments of the six launches of a graph chunk starting at buffer parity `par`.
 void chunk_args(lbmz_ctx* c, int par, unsigned e0) {
@@ -494,8 +531,8 @@ int launch_chunk(lbmz_ctx* c, int par, unsigned e0) {
 
 int launch_one(lbmz_ctx* c, int in, unsigned e) {
   PatchArgs a = args_for(c, in, in ^ 1, e);
-  if (c->exec_persistent) HIPCHK(c, launch_step_persistent(c->key, a, c->persist_grid, c->stream));
-  else HIPCHK(c, launch_step(c->key, a, c->npatch, c->stream));
+  if (c->exec_persistent) HIPCHK(c, launch_step_persistent(c->key, a, step_grid(c), c->stream));
+  else HIPCHK(c, launch_step(c->key, a, step_grid(c), c->stream));
   return LBMZ_OK;
 }
 
@@ -513,7 +550,13 @@ int lbmz_create(const lbmz_grid* grid, const lbmz_scheme* scheme, const lbmz_pat
   if (rc == LBMZ_OK && !patch) rc = fail(c, LBMZ_EINVAL, "null patch");
   if (rc == LBMZ_OK) {
     const int p = patch->p[0];
-    if (patch->p[1] != p || !(p == 8 || p == 16 || p == 32 || p == 64))
+    if (c->dim == 3 && (patch->p[1] != p || patch->p[2] != p || !(p == 16 || p == 32)))
+      rc = fail(c, LBMZ_EINVAL, "3-D patch must be cubic with p in {16, 32}");
+    else if (c->dim == 3 && patch->wavelet != LBMZ_BL53)
+      rc = fail(c, LBMZ_EINVAL, "3-D patches use the folded BL5/3 wavelet");
+    else if (c->dim == 3 && patch->values != LBMZ_VALUES_F32)
+      rc = fail(c, LBMZ_EINVAL, "3-D records store float32 values");
+    else if (patch->p[1] != p || !(p == 8 || p == 16 || p == 32 || p == 64))
       rc = fail(c, LBMZ_EINVAL, "patch must be square with p in {8, 16, 32, 64}");
     else if (c->n % p != 0)
       rc = fail(c, LBMZ_EINVAL, "grid size %d is not a multiple of the patch size %d", c->n, p);
@@ -531,7 +574,7 @@ int lbmz_create(const lbmz_grid* grid, const lbmz_scheme* scheme, const lbmz_pat
         rc = fail(c, LBMZ_EINVAL, "levels=%d outside [0, %d] for this wavelet and patch size", levels, cap);
       c->p = p;
       c->npx = c->n / p;
-      c->npatch = c->npx * c->npx;
+      c->npatch = c->npx * c->npx * (c->dim == 3 ? c->npx : 1);
       c->wavelet = patch->wavelet == LBMZ_BL53 ? W_BL53 : W_HAAR;
       c->s = c->wavelet == W_BL53 ? p + 1 : p;
       c->levels = levels;
@@ -555,6 +598,15 @@ int lbmz_create(const lbmz_grid* grid, const lbmz_scheme* scheme, const lbmz_pat
     } else if ((size_t)maxlds < lds) {
       rc = fail(c, LBMZ_EINVAL, "patch needs %zu bytes of LDS, device allows %d", lds, maxlds);
     }
+  }
+  if (rc == LBMZ_OK && c->dim == 3) {
+    int ncu = 0, per_cu = 0;
+    const void* fn = step_kernel_entry(c->key, true);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || !fn ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kernel_threads(c->key), 0) != hipSuccess)
+      rc = fail(c, LBMZ_EDEVICE, "cannot size the 3-D step grid");
+    c->slots3 = std::max(1, std::min(c->npatch, ncu * std::max(1, per_cu)));
+    c->persist_grid = c->slots3;
   }
   if (rc == LBMZ_OK) {
     PatchArgs& a = c->base;
@@ -644,7 +696,7 @@ int lbmz_set_field(lbmz_ctx* c, int field, const void* src, size_t bytes, int sr
 int lbmz_set_macroscopic(lbmz_ctx* c, const void* rho, const void* ux, const void* uy, size_t bytes_each,
                          int on_device) {
   if (!c || !rho || !ux || !uy) return LBMZ_EINVAL;
-  if (c->scheme != S_LBM) return fail(c, LBMZ_EINVAL, "macroscopic set-up is for the LBM scheme");
+  if (c->scheme != S_LBM) return fail(c, LBMZ_EINVAL, "macroscopic set-up is for the D2Q9 scheme (3-D: lbmz_set_macroscopic3)");
   if (bytes_each != field_bytes(c)) return fail(c, LBMZ_EINVAL, "expected %zu bytes per field", field_bytes(c));
   int rc = ensure_buffers(c);
   if (rc) return rc;
@@ -698,8 +750,11 @@ int lbmz_step(lbmz_ctx* c, int n) {
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   if (c->reference) {
     for (int k = 0; k < n; ++k) {
-      HIPCHK(c, launch_reference_step(c->dtype, c->scheme, c->dense[c->cur], c->dense[c->cur ^ 1], c->n, c->base,
-                                      c->stream));
+      if (c->scheme == S_LBM3)
+        HIPCHK(c, launch_reference_step3(c->dense[c->cur], c->dense[c->cur ^ 1], c->n, c->base.omega, c->stream));
+      else
+        HIPCHK(c, launch_reference_step(c->dtype, c->scheme, c->dense[c->cur], c->dense[c->cur ^ 1], c->n, c->base,
+                                        c->stream));
       c->cur ^= 1;
     }
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
@@ -812,7 +867,7 @@ int lbmz_stats(lbmz_ctx* c, lbmz_stats_t* out) {
   out->ms_last_call = c->ms_last;
   if (c->reference) {
     const int nb = 256;
-    HIPCHK(c, launch_dense_totals(c->dtype, c->dense[c->cur], c->nfields, c->n, c->partials[0], nb, c->stream));
+    HIPCHK(c, launch_dense_totals(c->dtype, c->dense[c->cur], c->nfields, cells(c), c->partials[0], nb, c->stream));
     std::vector<double> part((size_t)nb * c->nfields);
     HIPCHK(c, hipMemcpyAsync(part.data(), c->partials[0], part.size() * sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
@@ -824,7 +879,7 @@ int lbmz_stats(lbmz_ctx* c, lbmz_stats_t* out) {
     }
     out->store_bytes = out->dense_bytes;
     out->capacity_bytes = out->dense_bytes;
-    out->nnz_total = (int64_t)c->n * c->n * c->nfields;
+    out->nnz_total = (int64_t)cells(c) * c->nfields;
     out->ratio = 1.0;
     return LBMZ_OK;
   }
@@ -857,6 +912,80 @@ int lbmz_stats(lbmz_ctx* c, lbmz_stats_t* out) {
   out->capacity_bytes = c->cap_bytes;
   out->ratio = (double)out->dense_bytes / (double)out->store_bytes;
   return LBMZ_OK;
+}
+
+int lbmz_get_totals(lbmz_ctx* c, double* out, int count) {
+  if (!c || !out) return LBMZ_EINVAL;
+  if (count != c->nfields) return fail(c, LBMZ_EINVAL, "expected %d totals, got %d", c->nfields, count);
+  int rc = ensure_buffers(c);
+  if (rc) return rc;
+  rc = commit(c);
+  if (rc) return rc;
+  if (c->reference) {
+    const int nb = 256;
+    HIPCHK(c, launch_dense_totals(c->dtype, c->dense[c->cur], c->nfields, cells(c), c->partials[0], nb, c->stream));
+    std::vector<double> part((size_t)nb * c->nfields);
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partials[0], part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int f = 0; f < c->nfields; ++f) {
+      double s = 0.0;
+      for (int b = 0; b < nb; ++b) s += part[(size_t)f * nb + b];
+      out[f] = s;
+    }
+    return LBMZ_OK;
+  }
+  const size_t ne = (size_t)c->npatch * c->nfields;
+  std::vector<double> part(ne, 0.0);
+  if (c->have_state) {
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partials[c->cur], ne * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  for (int f = 0; f < c->nfields; ++f) {
+    double s = 0.0;
+    for (int q = 0; q < c->npatch; ++q) s += part[(size_t)q * c->nfields + f];
+    out[f] = s;
+  }
+  return LBMZ_OK;
+}
+
+int lbmz_set_macroscopic3(lbmz_ctx* c, const void* rho, const void* ux, const void* uy, const void* uz,
+                          size_t bytes_each, int on_device) {
+  if (!c || !rho || !ux || !uy || !uz) return LBMZ_EINVAL;
+  if (c->scheme != S_LBM3) return fail(c, LBMZ_EINVAL, "lbmz_set_macroscopic3 is for the D3Q19 scheme");
+  if (bytes_each != field_bytes(c)) return fail(c, LBMZ_EINVAL, "expected %zu bytes per field", field_bytes(c));
+  int rc = ensure_buffers(c);
+  if (rc) return rc;
+  void* tmp = dalloc(c, 4 * bytes_each);
+  if (!tmp) return fail(c, LBMZ_ENOMEM, "temporary allocation failed");
+  uint8_t* t8 = static_cast<uint8_t*>(tmp);
+  rc = copy_in(c, t8, rho, bytes_each, on_device);
+  if (!rc) rc = copy_in(c, t8 + bytes_each, ux, bytes_each, on_device);
+  if (!rc) rc = copy_in(c, t8 + 2 * bytes_each, uy, bytes_each, on_device);
+  if (!rc) rc = copy_in(c, t8 + 3 * bytes_each, uz, bytes_each, on_device);
+  void* dst = nullptr;
+  if (!rc) {
+    if (c->reference) {
+      dst = c->dense[c->cur];
+    } else {
+      rc = ensure_staging(c, false);
+      dst = c->dense[0];
+    }
+  }
+  if (!rc) {
+    hipError_t e = launch_equilibrium3(t8, t8 + bytes_each, t8 + 2 * bytes_each, t8 + 3 * bytes_each, dst, c->n,
+                                       c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail(c, LBMZ_EDEVICE, "equilibrium kernel: %s", hipGetErrorString(e));
+  }
+  dfree(c, tmp);
+  if (rc) return rc;
+  if (c->reference) {
+    c->steps = 0;
+    return LBMZ_OK;
+  }
+  c->staging_dirty = true;
+  return commit(c);
 }
 
 int lbmz_store_size(lbmz_ctx* c, int64_t* pool_bytes, int64_t* table_entries) {
@@ -1016,6 +1145,7 @@ int lbmz_set_patch_eps(lbmz_ctx* c, const double* eps, size_t count, int on_devi
     return LBMZ_OK;
   }
   if (!eps) return LBMZ_EINVAL;
+  if (c->dim == 3) return fail(c, LBMZ_EINVAL, "per-patch thresholds are for 2-D grids");
   if (count != (size_t)c->npatch)
     return fail(c, LBMZ_EINVAL, "expected %d per-patch thresholds, got %zu", c->npatch, count);
   if (!on_device) {
@@ -1124,6 +1254,7 @@ void lbmz_destroy(lbmz_ctx* c) {
     dfree(c, c->dense[b]);
   }
   dfree(c, c->ctrl);
+  dfree(c, c->scratch);
   dfree(c, c->eps_patch);
   dfree(c, c->features);
   if (c->ctrl_host) (void)hipHostFree(c->ctrl_host);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblbmz.so")
 LBMZ_OK, LBMZ_EINVAL, LBMZ_ENOMEM, LBMZ_EDEVICE, LBMZ_EOVERFLOW, LBMZ_ENAN, LBMZ_ESTATE = 0, -1, -2, -3, -4, -5, -6
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "ENAN", -6: "ESTATE"}
 
-SCHEMES = {"fv_upwind": 0, "d2q9_bgk": 1, "euler_rusanov": 2}
+SCHEMES = {"fv_upwind": 0, "d2q9_bgk": 1, "euler_rusanov": 2, "d3q19_bgk": 3}
 WAVELETS = {"haar": 0, "bl53": 1}
 RULES = {"capped": 0, "constant": 1, "accum": 2}
 DTYPES = {"f32": 0, "f64": 1}
@@ -79,6 +79,8 @@ def library() -> ct.CDLL:
         "lbmz_set_pool_capacity": ([vp, ct.c_int64], ct.c_int),
         "lbmz_set_field": ([vp, ct.c_int, vp, ct.c_size_t, ct.c_int], ct.c_int),
         "lbmz_set_macroscopic": ([vp, vp, vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
+        "lbmz_set_macroscopic3": ([vp, vp, vp, vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
+        "lbmz_get_totals": ([vp, vp, ct.c_int], ct.c_int),
         "lbmz_step": ([vp, ct.c_int], ct.c_int),
         "lbmz_decompress_field": ([vp, ct.c_int, vp, ct.c_size_t, ct.c_int], ct.c_int),
         "lbmz_stats": ([vp, P(Stats)], ct.c_int),
@@ -144,15 +146,16 @@ class Context:
         self.wavelet, self.levels, self.eps, self.rule = wavelet, levels, eps, rule
         self.reference = reference
         self.np_dtype = NP_DTYPES[dtype]
-        self.nfields = {"d2q9_bgk": 9, "euler_rusanov": 4}.get(scheme, 1)
+        self.nfields = {"d2q9_bgk": 9, "euler_rusanov": 4, "d3q19_bgk": 19}.get(scheme, 1)
+        self.dim = 3 if scheme == "d3q19_bgk" else 2
         self.s = (p + 1 if wavelet == "bl53" else p) if not reference else n
-        g = Grid(2, (ct.c_int64 * 3)(n, n, 1), 1, 1.0 / n)
+        g = Grid(self.dim, (ct.c_int64 * 3)(n, n, n if self.dim == 3 else 1), 1, 1.0 / n)
         sc = Scheme(SCHEMES[scheme], DTYPES[dtype], (ct.c_double * 3)(vel[0], vel[1], 0.0), cfl, tau, gamma)
         h = ct.c_void_p()
         if reference:
             rc = self._lib.lbmz_create_reference(ct.byref(g), ct.byref(sc), ct.byref(h))
         else:
-            pt = Patch((ct.c_int * 3)(p, p, 1), WAVELETS[wavelet], RULES[rule], VALUES[values])
+            pt = Patch((ct.c_int * 3)(p, p, p if self.dim == 3 else 1), WAVELETS[wavelet], RULES[rule], VALUES[values])
             rc = self._lib.lbmz_create(ct.byref(g), ct.byref(sc), ct.byref(pt), levels, eps, ct.byref(h))
         if rc != LBMZ_OK:
             raise LbmzError(rc, "create failed (invalid geometry, levels, scheme or no kernel for the key)")
@@ -215,12 +218,19 @@ class Context:
         self._check(self._lib.lbmz_set_field(self._h, field, ptr, nb, dev))
         del keep
 
-    def set_macroscopic(self, rho, ux, uy):
-        bufs = [_buffer(x, self.np_dtype) for x in (rho, ux, uy)]
+    def set_macroscopic(self, rho, ux, uy, uz=None):
+        """Equilibrium populations of the given density and velocity (``uz`` for D3Q19)."""
+        arrs = (rho, ux, uy) if self.dim == 2 else (rho, ux, uy, uz)
+        if any(x is None for x in arrs):
+            raise ValueError("the D3Q19 scheme needs uz")
+        bufs = [_buffer(x, self.np_dtype) for x in arrs]
         if len({b[1] for b in bufs}) != 1 or len({b[2] for b in bufs}) != 1:
-            raise ValueError("rho, ux, uy must have the same size and location")
-        self._check(self._lib.lbmz_set_macroscopic(self._h, bufs[0][0], bufs[1][0], bufs[2][0], bufs[0][1],
-                                                   bufs[0][2]))
+            raise ValueError("the fields must have the same size and location")
+        ptrs = [b[0] for b in bufs]
+        if self.dim == 3:
+            self._check(self._lib.lbmz_set_macroscopic3(self._h, *ptrs, bufs[0][1], bufs[0][2]))
+        else:
+            self._check(self._lib.lbmz_set_macroscopic(self._h, *ptrs, bufs[0][1], bufs[0][2]))
 
     def set_coefficients(self, coef):
         ptr, nb, dev, keep = _buffer(coef, self.np_dtype)
@@ -268,7 +278,7 @@ class Context:
 
     def decompress_field(self, field: int, out=None):
         if out is None:
-            out = np.empty((self.n, self.n), dtype=self.np_dtype)
+            out = np.empty((self.n,) * self.dim, dtype=self.np_dtype)
         ptr, nb, dev, keep = _buffer(out, self.np_dtype)
         if not dev and keep is not out:
             raise ValueError("host output must be a contiguous array of the context dtype")
@@ -276,15 +286,21 @@ class Context:
         return out
 
     def fields(self) -> np.ndarray:
-        """All fields on the host, ``[nfields, n, n]``."""
+        """All fields on the host, ``[nfields, n, n]`` (``[nfields, n, n, n]`` in 3-D)."""
         return np.stack([self.decompress_field(f) for f in range(self.nfields)])
 
     def stats(self) -> dict:
         st = Stats()
         self._check(self._lib.lbmz_stats(self._h, ct.byref(st)))
         d = {k: getattr(st, k) for k, _ in Stats._fields_}
-        d["totals"] = list(st.totals)[:self.nfields]
+        d["totals"] = self.totals().tolist()
         return d
+
+    def totals(self) -> np.ndarray:
+        """FP64 per-field (trapezoid-weighted) sums of the decompressed state, ``[nfields]``."""
+        out = np.zeros(self.nfields, dtype=np.float64)
+        self._check(self._lib.lbmz_get_totals(self._h, ct.c_void_p(out.ctypes.data), self.nfields))
+        return out
 
     # -- compressed store -------------------------------------------------------
     def store(self):
@@ -480,3 +496,26 @@ def decode_records(table: np.ndarray, pool: bytes, s: int, dtype, values: str = 
     out = np.zeros_like(seq)
     out[:, :, order] = seq
     return out.reshape(npatch, nf, s, s)
+
+
+def decode_records3(table: np.ndarray, pool: bytes, s: int) -> np.ndarray:
+    """Coefficient tiles ``float32 [npatch, nfields, s, s, s]`` of a 3-D store
+    (record index k = x + s y + s^2 z; host-side reader of include/lbmz.h)."""
+    npatch, nf = table.shape[:2]
+    nc = s ** 3
+    w = (nc + 63) // 64
+    out = np.zeros((npatch, nf, nc), dtype=np.float32)
+    buf = np.frombuffer(pool, dtype=np.uint8)
+    for q in range(npatch):
+        for f in range(nf):
+            off = int(table[q, f, 0]) * 16
+            word = int(table[q, f, 1])
+            nnz = word & (MASK_BIT - 1)
+            vb = (4 * nnz + 7) // 8 * 8
+            vals = buf[off:off + 4 * nnz].view("<f4")
+            if word & MASK_BIT:
+                bits = np.unpackbits(buf[off + vb:off + vb + 8 * w], bitorder="little")[:nc].astype(bool)
+                out[q, f, bits] = vals
+            else:
+                out[q, f, buf[off + vb:off + vb + 2 * nnz].view("<u2").astype(np.int64)] = vals
+    return out.reshape(npatch, nf, s, s, s)

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "lbmz.h")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbmz_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lbmz_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():

@@ -1,0 +1,209 @@
+"""GPU parity of the 3-D D3Q19 patch loop (persistent step kernel with
+per-workgroup scratch, halo planes and lines, flat-order records).
+
+* Set-up and decompression reproduce the oracle's equilibrium state.
+* At eps = 0 the compressed loop equals the uncompressed reference kernel and
+  the oracle's plain scheme.
+* Records written from given coefficients are byte-identical to the oracle's.
+* One step from a common state matches the oracle's step (keep / drop flips
+  only at round-off distance from a threshold).
+* Several steps at eps > 0 stay close to the oracle, conserve mass and
+  momentum, and absorb a pool overflow with the same result.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lbmz_oracle3d as O3
+from synth import taylor_green_jets_3d
+
+from gpu_helpers import require_gpu, torch  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+TAU = 0.55
+
+
+def _say(*args):
+    print("[case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _ctx(n, p, levels, eps, reference=False, **kw):
+    from paper_2302_09883_amd import Context
+    return Context(n, scheme="d3q19_bgk", dtype="f32", p=p, wavelet="bl53", levels=levels, eps=eps, tau=TAU,
+                   reference=reference, **kw)
+
+
+def _macro(n, seed):
+    return taylor_green_jets_3d(n, seed=seed, n_jets=3, dtype=np.float32)
+
+
+def _oracle_state(n, seed, dtype=np.float64):
+    rho, ux, uy, uz = (a.astype(np.float64) for a in _macro(n, seed))
+    return O3.d3q19_equilibrium(rho, ux, uy, uz).astype(dtype)
+
+
+def _tiles(ctx):
+    from paper_2302_09883_amd import decode_records3
+    table, pool = ctx.store()
+    return decode_records3(table, pool, ctx.s), table, pool
+
+
+@pytest.mark.parametrize("n,p,levels", [(32, 16, 3), (64, 32, 3)])
+def test_setup_and_decompression(n, p, levels):
+    _say("3d setup", n, p, levels)
+    ctx = _ctx(n, p, levels, 0.0)
+    ctx.set_macroscopic(*_macro(n, 1))
+    got = ctx.fields()
+    want = _oracle_state(n, 1)
+    assert got.shape == (19, n, n, n)
+    assert np.max(np.abs(got - want)) <= 2e-6 * np.max(np.abs(want))
+    t = ctx.totals()
+    assert np.allclose(t, want.sum(axis=(1, 2, 3)), rtol=2e-6)
+
+
+@pytest.mark.parametrize("n,p,levels", [(48, 16, 3), (64, 32, 3)])
+def test_eps0_equals_reference_and_oracle(n, p, levels):
+    _say("3d eps0", n, p, levels)
+    steps = 6
+    ref = _ctx(n, p, levels, 0.0, reference=True)
+    ref.set_macroscopic(*_macro(n, 2))
+    cmp = _ctx(n, p, levels, 0.0)
+    cmp.set_macroscopic(*_macro(n, 2))
+    ref.step(steps)
+    cmp.step(steps)
+    a, b = ref.fields(), cmp.fields()
+    f = _oracle_state(n, 2)
+    for _ in range(steps):
+        f = O3.dense_step3(f, TAU)
+    rel = np.linalg.norm(b - f) / np.linalg.norm(f)
+    assert rel <= 1e-5, rel
+    assert np.linalg.norm(a - f) / np.linalg.norm(f) <= 1e-5
+    assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(f))
+
+
+@pytest.mark.parametrize("density", [0.002, 0.3])
+def test_records_from_given_coefficients_are_the_oracles(density):
+    _say("3d records", density)
+    n, p, levels, eps = 32, 16, 3, 1e-3
+    g = O3.Geometry3(n, p, levels)
+    rng = np.random.default_rng(5)
+    coef = (rng.standard_normal((g.npatch, 19, g.s, g.s, g.s)) * 1e-2).astype(np.float32)
+    coef[rng.random(coef.shape) >= density] = 0
+    coef[:, :, ::8, ::8, ::8] = 0.05          # samples (never thresholded)
+    ctx = _ctx(n, p, levels, eps)
+    ctx.set_coefficients(coef)
+    twin = O3.CompressedRun3(g, TAU, eps, dtype=np.float32)
+    twin.set_coefficients(coef)
+    got, table, pool = _tiles(ctx)
+    assert np.array_equal(got, twin.coef)
+    want_table, _ = twin.store()
+    assert np.array_equal(table[..., 1], want_table[..., 1])
+    for q in range(g.npatch):
+        for f in range(19):
+            rec = O3.encode_record3(twin.coef[q, f])
+            off = int(table[q, f, 0]) * 16
+            assert pool[off:off + len(rec)] == rec, (q, f)
+    st = ctx.stats()
+    assert st["store_bytes"] == twin.store_bytes()
+    assert st["mask_records"] + st["list_records"] == g.npatch * 19
+    if density < 0.01:
+        assert st["list_records"] > 0
+    else:
+        assert st["mask_records"] > 0
+
+
+@pytest.mark.parametrize("n,p,levels,eps", [(48, 16, 3, 1e-4), (64, 32, 3, 1e-4), (32, 16, 2, 1e-3)])
+def test_one_step_from_common_state(n, p, levels, eps):
+    _say("3d one step", n, p, levels, eps)
+    g = O3.Geometry3(n, p, levels)
+    twin = O3.CompressedRun3(g, TAU, eps, dtype=np.float32)
+    twin.set_grid(_oracle_state(n, 3, np.float32))
+    twin.step(1)
+    table, pool = twin.store()
+    ctx = _ctx(n, p, levels, eps)
+    ctx.put_store(table, pool)
+    ctx.step(1)
+    twin.step(1)
+    got, _, _ = _tiles(ctx)
+    want = twin.coef
+    u = np.finfo(np.float32).eps
+    delta = 256 * u * float(np.max(np.abs(want)))
+    flip = (got != 0) != (want != 0)
+    near = np.abs(np.abs(np.where(got != 0, got, want)) - twin.thr) <= delta
+    assert np.all(near[flip]), int(flip.sum())
+    assert np.max(np.abs(np.where(flip, 0.0, got - want))) <= delta
+    assert flip.sum() <= 1e-4 * flip.size
+    assert 0 < np.count_nonzero(got) < got.size
+
+
+def test_multi_step_close_to_oracle_and_conserving():
+    _say("3d multi step")
+    n, p, levels, eps, steps = 48, 16, 3, 1e-4, 8
+    g = O3.Geometry3(n, p, levels)
+    twin = O3.CompressedRun3(g, TAU, eps)
+    twin.set_grid(_oracle_state(n, 4))
+    ctx = _ctx(n, p, levels, eps)
+    ctx.set_macroscopic(*_macro(n, 4))
+    t0 = ctx.totals()
+    ctx.step(steps)
+    twin.step(steps)
+    a, b = ctx.fields(), twin.grid()
+    rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert rel <= 1e-4, rel
+    # kept coefficients (the float64 twin's ratio would count 8-byte values)
+    assert abs(ctx.stats()["nnz_total"] / twin.nnz().sum() - 1) <= 0.01
+    t1 = ctx.totals()
+    c = O3.D3Q19_C.astype(np.float64)
+    assert abs(t1.sum() - t0.sum()) <= 2e-6 * abs(t0.sum())
+    assert np.allclose(t1 @ c, t0 @ c, atol=2e-6 * abs(t0.sum()))
+    assert np.allclose(t1, twin.field_totals(), rtol=1e-5)
+
+
+def test_pool_overflow_is_absorbed():
+    _say("3d overflow")
+    n, p, levels, eps = 32, 16, 3, 1e-5
+    base = _ctx(n, p, levels, eps)
+    small = _ctx(n, p, levels, eps, pool_capacity=4096)
+    for c in (base, small):
+        c.set_macroscopic(*_macro(n, 5))
+        c.step(5)
+    assert small.stats()["regrows"] >= 1
+    a, _, _ = _tiles(base)
+    b, _, _ = _tiles(small)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert base.stats()["store_bytes"] == small.stats()["store_bytes"]
+
+
+def test_graph_mode_gives_the_same_records():
+    _say("3d graph")
+    n, p, levels, eps = 32, 16, 3, 1e-4
+    a = _ctx(n, p, levels, eps)
+    b = _ctx(n, p, levels, eps)
+    b.set_execution(False, True)
+    for c in (a, b):
+        c.set_macroscopic(*_macro(n, 6))
+        c.step(13)
+    ta, _, _ = _tiles(a)
+    tb, _, _ = _tiles(b)
+    assert np.array_equal(ta.view(np.uint32), tb.view(np.uint32))
+
+
+def test_invalid_3d_configurations_are_rejected():
+    from paper_2302_09883_amd import LbmzError
+    with pytest.raises(LbmzError):
+        _ctx(32, 8, 2, 1e-4)          # 8^3 patches: no kernel
+    with pytest.raises(LbmzError):
+        _ctx(48, 16, 4, 1e-4)         # L = J: no update step, no conservation
+    with pytest.raises(LbmzError):
+        _ctx(40, 16, 3, 1e-4)         # n not a multiple of p
+    ctx = _ctx(32, 16, 3, 1e-4)
+    with pytest.raises(LbmzError):
+        ctx.set_patch_eps(np.full(8, 1e-4))
