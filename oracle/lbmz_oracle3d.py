@@ -179,29 +179,37 @@ def assemble_grid3(tiles: np.ndarray, g: Geometry3) -> np.ndarray:
     return out
 
 
-def gather_ghosts3(tiles: np.ndarray, g: Geometry3) -> np.ndarray:
-    """Tiles with a one-node ghost layer, ``[npatch, m, s + 2, s + 2, s + 2]``.
+def gather_ghosts3_one(tile_of, g: Geometry3, q: int) -> np.ndarray:
+    """Tile ``q`` with a one-node ghost layer, ``[m, s + 2, s + 2, s + 2]``.
 
-    Along each dimension, ghost node ``-1`` is node ``p - 1`` of the lower
-    neighbour and ghost node ``s`` is node ``1`` of the upper neighbour; nodes
-    off the tile in two or three dimensions come from the edge and corner
-    neighbours.  Every value is taken from the neighbours' tiles as given.
+    ``tile_of(k)`` gives tile ``k`` (``[m, s, s, s]``).  Along each dimension,
+    ghost node ``-1`` is node ``p - 1`` of the lower neighbour and ghost node
+    ``s`` is node ``1`` of the upper neighbour; nodes off the tile in two or
+    three dimensions come from the edge and corner neighbours.  Every value is
+    taken from the neighbours' tiles as given.
     """
     npx, p, s = g.npx, g.p, g.s
-    m = tiles.shape[1]
-    out = np.empty((g.npatch, m, s + 2, s + 2, s + 2), dtype=tiles.dtype)
     coord = np.arange(-1, s + 1)
     off = np.where(coord < 0, -1, np.where(coord >= s, 1, 0))
     loc = coord - p * off
-    for q in range(g.npatch):
-        px, py, pz = g.patch_coords(q)
-        nx = (px + off) % npx
-        ny = (py + off) % npx
-        nz = (pz + off) % npx
-        nb = nx[None, None, :] + npx * ny[None, :, None] + npx * npx * nz[:, None, None]
-        vals = tiles[nb, :, loc[:, None, None], loc[None, :, None], loc[None, None, :]]   # [s+2]^3 x m
-        out[q] = np.moveaxis(vals, -1, 0)
+    px, py, pz = g.patch_coords(q)
+    out = None
+    for oz in (-1, 0, 1):
+        for oy in (-1, 0, 1):
+            for ox in (-1, 0, 1):
+                k = (px + ox) % npx + npx * ((py + oy) % npx) + npx * npx * ((pz + oz) % npx)
+                t = tile_of(k)
+                if out is None:
+                    out = np.empty((t.shape[0], s + 2, s + 2, s + 2), dtype=t.dtype)
+                iz, iy, ix = (np.flatnonzero(off == o) for o in (oz, oy, ox))
+                out[:, iz[:, None, None], iy[None, :, None], ix[None, None, :]] = \
+                    t[:, loc[iz][:, None, None], loc[iy][None, :, None], loc[ix][None, None, :]]
     return out
+
+
+def gather_ghosts3(tiles: np.ndarray, g: Geometry3) -> np.ndarray:
+    """All tiles with their ghost layer, ``[npatch, m, s + 2, s + 2, s + 2]``."""
+    return np.stack([gather_ghosts3_one(lambda k: tiles[k], g, q) for q in range(g.npatch)])
 
 
 # ---------------------------------------------------------------------------

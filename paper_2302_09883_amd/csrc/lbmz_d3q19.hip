@@ -15,8 +15,9 @@
 //   B  BGK collision node by node in scratch (S4);
 //   C  for every population: load it into LDS, forward transform x, y, z
 //      (S5), hard threshold (S6), compaction into a record of the output pool
-//      (S7), inverse transform of the thresholded tile, FP64 trapezoid total
-//      (S9) and export of the planes and lines the neighbours pull from (S8).
+//      (S7), FP64 trapezoid total from the coarse samples (S9), inverse
+//      transform of the thresholded tile and export of the planes and lines
+//      the neighbours pull from (S8).
 // The step kernel is persistent: one workgroup per scratch slice takes
 // patches from an atomic work queue until none is left.
 //
@@ -97,11 +98,36 @@ __device__ __forceinline__ uint32_t scan_counts(uint32_t* a, int n, SM& sm) {
   return tot;
 }
 
+// Set bits of m below the calling lane.
+__device__ __forceinline__ uint32_t mbcnt64(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
 // ---------------------------------------------------------------------------
 // Lines of the tile in registers: DIR 0 = x-lines, 1 = y-lines, 2 = z-lines.
 // ---------------------------------------------------------------------------
-template <class C, int DIR, bool FWD>
-__device__ __forceinline__ void line_pass(float* tile, int L) {
+// S6 on a z-line after its forward transform: the x and y ranks are those of
+// the line, the z rank is that of the element (a compile-time index).  A
+// detail (a detail in at least one dimension) with |c| < eps * 2^r is zeroed,
+// r = max (capped), sum (accumulation) or 0 (constant) of the three ranks.
+template <class C>
+__device__ __forceinline__ void threshold_zline(float* v, int x, int y, int L, float eps, int rule) {
+  const int rx = dim_rank(x, L), ry = dim_rank(y, L);
+  const bool dxy = rx >= 0 || ry >= 0;
+  const int ax = rx < 0 ? 0 : rx, ay = ry < 0 ? 0 : ry;
+  const int rmax = ax > ay ? ax : ay, rsum = ax + ay;
+  const int lmask = (1 << L) - 1;
+#pragma unroll
+  for (int k = 0; k < C::S; ++k) {
+    const bool zs = (k & lmask) == 0;
+    const int rz = zs ? 0 : L - 1 - __builtin_ctz((unsigned)(k == 0 ? 1 : k));
+    const int r = rule == R_CAPPED ? (rmax > rz ? rmax : rz) : (rule == R_ACCUM ? rsum + rz : 0);
+    if ((dxy || !zs) && fabsf(v[k]) < ldexpf(eps, r)) v[k] = 0.f;
+  }
+}
+
+template <class C, int DIR, bool FWD, bool THR = false>
+__device__ __forceinline__ void line_pass(float* tile, int L, float eps = 0.f, int rule = 0) {
   using LF = Lift<float, C::S, W_BL53, 1, C::LMAX>;
   for (int l = threadIdx.x; l < C::S2; l += C::NT) {
     int base, stride;
@@ -121,17 +147,24 @@ __device__ __forceinline__ void line_pass(float* tile, int L) {
     for (int k = 0; k < C::S; ++k) v[k] = tile[base + k * stride];
     if constexpr (FWD) LF::fwd(v, L);
     else LF::inv(v, L);
+    if constexpr (THR) {
+      static_assert(DIR == 2, "the threshold rides on the last (z) forward pass");
+      const int y = l / C::S;
+      threshold_zline<C>(v, l - y * C::S, y, L, eps, rule);
+    }
 #pragma unroll
     for (int k = 0; k < C::S; ++k) tile[base + k * stride] = v[k];
   }
   __syncthreads();
 }
 
+// Forward transform x, y, z, and the hard threshold of Section 2.2 fused into
+// the z pass.
 template <class C>
-__device__ __forceinline__ void forward3(float* tile, int L) {
-  line_pass<C, 0, true>(tile, L);
-  line_pass<C, 1, true>(tile, L);
-  line_pass<C, 2, true>(tile, L);
+__device__ __forceinline__ void forward3_threshold(const PatchArgs& a, float* tile) {
+  line_pass<C, 0, true>(tile, a.levels);
+  line_pass<C, 1, true>(tile, a.levels);
+  line_pass<C, 2, true, true>(tile, a.levels, (float)a.eps, a.rule);
 }
 
 template <class C>
@@ -140,6 +173,29 @@ __device__ __forceinline__ void inverse3(float* tile, int L) {
   line_pass<C, 1, false>(tile, L);
   line_pass<C, 0, false>(tile, L);
 }
+
+// Optional per-phase clocks of the 3-D step (profiling builds compiled with
+// -DLBMZ_PHASE_CLOCK; the product build has none): accumulated wall-clock
+// ticks per workgroup and phase.
+#ifdef LBMZ_PHASE_CLOCK
+static __device__ unsigned long long lbmz_phase3[1024 * 16];
+#define P3_START() unsigned long long p3_t = wall_clock64()
+#define P3_MARK(k)                                                                  \
+  do {                                                                              \
+    if (threadIdx.x == 0 && blockIdx.x < 1024) {                                    \
+      const unsigned long long t_ = wall_clock64();                                 \
+      lbmz_phase3[blockIdx.x * 16 + (k)] += t_ - p3_t;                              \
+      p3_t = t_;                                                                    \
+    }                                                                               \
+  } while (0)
+#else
+#define P3_START() \
+  do {             \
+  } while (0)
+#define P3_MARK(k) \
+  do {             \
+  } while (0)
+#endif
 
 // ---------------------------------------------------------------------------
 // S1: record (patch q, field f) of the input store -> LDS tile
@@ -161,12 +217,26 @@ __device__ void expand_field(const PatchArgs& a, int q, int f, SM& sm) {
     if (tid < C::W) sm.pre[tid] = (uint32_t)__popcll(words[tid]);
     __syncthreads();
     scan_counts<C>(sm.pre, C::W, sm);
-    for (int c = wave; c < C::W; c += C::NW) {
-      const unsigned long long word = words[c];
-      const int t = 64 * c + lane;
-      const bool bit = ((word >> lane) & 1ull) != 0ull;
-      const float v = bit ? vals[sm.pre[c] + (uint32_t)__popcll(word & below(lane))] : 0.f;
-      if (t < C::S3) sm.tile[t] = v;
+    constexpr int U = 4;   // chunks per wave and iteration (independent loads in flight)
+    for (int c0 = wave; c0 < C::W; c0 += U * C::NW) {
+      unsigned long long word[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * C::NW;
+        word[u] = c < C::W ? words[c] : 0ull;
+      }
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * C::NW;
+        const bool bit = ((word[u] >> lane) & 1ull) != 0ull;
+        v[u] = bit ? vals[sm.pre[c] + mbcnt64(word[u])] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = 64 * (c0 + u * C::NW) + lane;
+        if (t < C::S3) sm.tile[t] = v[u];
+      }
     }
   } else {
     const uint16_t* idx = reinterpret_cast<const uint16_t*>(rec + vb);
@@ -178,42 +248,60 @@ __device__ void expand_field(const PatchArgs& a, int q, int f, SM& sm) {
 }
 
 // ---------------------------------------------------------------------------
-// S6 + S7: threshold the transformed tile in LDS and append its record to the
-// output pool.  Returns false when the pool is full (flag raised).
+// S7 (with THR also S6): compact the thresholded tile in LDS into a record
+// appended to the output pool.  Returns false when the pool is full (flag
+// raised).
 // ---------------------------------------------------------------------------
-template <class C, class SM>
+template <class C, bool THR, class SM>
 __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = wave_id();
   const int L = a.levels;
   const float eps = (float)a.eps;
-  // S6: zero the dropped details (the inverse for the export needs them zero)
-  for (int t = tid; t < C::S3; t += C::NT) {
-    const int z = t / C::S2;
-    const int r = t - z * C::S2;
-    const int y = r / C::S;
-    const int x = r - y * C::S;
-    const int rx = dim_rank(x, L), ry = dim_rank(y, L), rz = dim_rank(z, L);
-    if (rx < 0 && ry < 0 && rz < 0) continue;   // pure sample: never zeroed
-    const int ax = rx < 0 ? 0 : rx, ay = ry < 0 ? 0 : ry, az = rz < 0 ? 0 : rz;
-    int rk = 0;
-    if (a.rule == R_CAPPED) rk = max(ax, max(ay, az));
-    else if (a.rule == R_ACCUM) rk = ax + ay + az;
-    const float thr = ldexpf(eps, rk);
-    const float c = sm.tile[t];
-    if (fabsf(c) < thr) sm.tile[t] = 0.f;
+  P3_START();
+  // counts: one ballot per 64-node chunk
+  constexpr int U = 4;   // chunks per wave and iteration (independent LDS reads in flight)
+  for (int c0 = wave; c0 < C::W; c0 += U * C::NW) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = 64 * (c0 + u * C::NW) + lane;
+      v[u] = t < C::S3 ? sm.tile[t] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * C::NW;
+      if constexpr (THR) {
+        // S6 here (coefficients given directly): zero a dropped detail in the
+        // tile, the inverse for the export needs it zero
+        const int t = 64 * c + lane;
+        if (t < C::S3) {
+          const int z = t / C::S2;
+          const int r = t - z * C::S2;
+          const int y = r / C::S;
+          const int x = r - y * C::S;
+          const int rx = dim_rank(x, L), ry = dim_rank(y, L), rz = dim_rank(z, L);
+          if (rx >= 0 || ry >= 0 || rz >= 0) {   // a detail (pure samples are never zeroed)
+            const int ax = rx < 0 ? 0 : rx, ay = ry < 0 ? 0 : ry, az = rz < 0 ? 0 : rz;
+            int rk = 0;
+            if (a.rule == R_CAPPED) rk = max(ax, max(ay, az));
+            else if (a.rule == R_ACCUM) rk = ax + ay + az;
+            if (fabsf(v[u]) < ldexpf(eps, rk)) {
+              v[u] = 0.f;
+              sm.tile[t] = 0.f;
+            }
+          }
+        }
+      }
+      const unsigned long long bits = __ballot(v[u] != 0.f);
+      if (lane == 0 && c < C::W) sm.pre[c] = (uint32_t)__popcll(bits);
+    }
   }
   __syncthreads();
-  // S7: counts per 64-node chunk, prefix, one bump allocation per record
-  for (int c = wave; c < C::W; c += C::NW) {
-    const int t = 64 * c + lane;
-    const float v = t < C::S3 ? sm.tile[t] : 0.f;
-    const unsigned long long bits = __ballot(v != 0.f);
-    if (lane == 0) sm.pre[c] = (uint32_t)__popcll(bits);
-  }
-  __syncthreads();
+  P3_MARK(10);
   const uint32_t nnz = scan_counts<C>(sm.pre, C::W, sm);
+  P3_MARK(11);
   const bool ismask = !(2u * nnz < 8u * (uint32_t)C::W);
   const uint32_t vb = (4u * nnz + 7u) & ~7u;
   const uint32_t mb = ismask ? 8u * (uint32_t)C::W : 2u * nnz;
@@ -233,21 +321,34 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
     sm.misc[1] = (uint32_t)base;
   }
   __syncthreads();
+  P3_MARK(12);
   if (!sm.misc[0]) return false;
   uint8_t* rec = a.pool_out + 16ull * sm.misc[1];
   float* vals = reinterpret_cast<float*>(rec);
   uint16_t* idx = reinterpret_cast<uint16_t*>(rec + vb);
   unsigned long long* words = reinterpret_cast<unsigned long long*>(rec + vb);
-  for (int c = wave; c < C::W; c += C::NW) {
-    const int t = 64 * c + lane;
-    const float v = t < C::S3 ? sm.tile[t] : 0.f;
-    const unsigned long long bits = __ballot(v != 0.f);
-    const uint32_t k = sm.pre[c] + (uint32_t)__popcll(bits & below(lane));
-    if (v != 0.f) {
-      vals[k] = v;
-      if (!ismask) idx[k] = (uint16_t)t;
+  for (int c0 = wave; c0 < C::W; c0 += U * C::NW) {
+    float v[U];
+    uint32_t pre[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * C::NW;
+      const int t = 64 * c + lane;
+      v[u] = t < C::S3 ? sm.tile[t] : 0.f;
+      pre[u] = c < C::W ? sm.pre[c] : 0u;
     }
-    if (ismask && lane == 0) words[c] = bits;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * C::NW;
+      const int t = 64 * c + lane;
+      const unsigned long long bits = __ballot(v[u] != 0.f);
+      const uint32_t k = pre[u] + mbcnt64(bits);
+      if (v[u] != 0.f) {
+        vals[k] = v[u];
+        if (!ismask) idx[k] = (uint16_t)t;
+      }
+      if (ismask && lane == 0 && c < C::W) words[c] = bits;
+    }
   }
   // zero padding: after the values, and from the end of the indices or
   // words to the end of the record
@@ -255,24 +356,33 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
   const uint32_t tail0 = (vb + mb) / 2u, tail1 = rb16 * 8u;
   uint16_t* h = reinterpret_cast<uint16_t*>(rec);
   if (tid < (int)(tail1 - tail0)) h[tail0 + tid] = 0;
+  P3_MARK(13);
   return true;
 }
 
 // ---------------------------------------------------------------------------
-// S9: FP64 trapezoid total of the reconstructed tile (1/2 per shared
-// bordering node and dimension); a non-finite total raises the abort flag.
+// S9: FP64 trapezoid total of the reconstructed tile from the coefficient tile
+// in LDS.  By the conservation identity of the lifting (equation
+// "conservation", once per dimension), the trapezoid mass of the
+// reconstruction is 8^L times the trapezoid mass of the coarse samples (the
+// nodes whose three indices are multiples of 2^L), whatever the details.
+// With CHECK a non-finite total raises the abort flag: the forward lifting
+// carries every element of a line into the line's coarse samples, so a
+// non-finite value anywhere makes a sample, and the total, non-finite.
 // ---------------------------------------------------------------------------
 template <class C, bool CHECK, class SM>
 __device__ void total_field(const PatchArgs& a, int q, int f, SM& sm) {
   const int tid = threadIdx.x;
+  const int L = a.levels;
+  const int sc = ((C::S - 1) >> L) + 1;   // coarse samples per dimension
   double part = 0.0;
-  for (int t = tid; t < C::S3; t += C::NT) {
-    const int z = t / C::S2;
-    const int r = t - z * C::S2;
-    const int y = r / C::S;
-    const int x = r - y * C::S;
-    const int nb = (x == 0 || x == C::P) + (y == 0 || y == C::P) + (z == 0 || z == C::P);
-    part += ldexp((double)sm.tile[t], -nb);
+  for (int n = tid; n < sc * sc * sc; n += C::NT) {
+    const int k = n / (sc * sc);
+    const int r = n - k * sc * sc;
+    const int j = r / sc;
+    const int i = r - j * sc;
+    const int nb = (i == 0 || i == sc - 1) + (j == 0 || j == sc - 1) + (k == 0 || k == sc - 1);
+    part += ldexp((double)sm.tile[(i << L) + C::S * (j << L) + C::S2 * (k << L)], 3 * L - nb);
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) part += __shfl_down(part, d, 64);
@@ -347,41 +457,19 @@ __device__ void export_field(const PatchArgs& a, int q, int f, SM& sm) {
   }
 }
 
-// Value of population f pulled from (mx, my, mz), a node off the tile in one
-// or two dimensions, out of the halo exported by the neighbour owning it.
-template <class C>
-__device__ __forceinline__ float halo_value(const PatchArgs& a, int q, const int* cf, const int* sl, int mx, int my,
-                                            int mz) {
-  const int ox = mx < 0 ? -1 : (mx >= C::S ? 1 : 0);
-  const int oy = my < 0 ? -1 : (my >= C::S ? 1 : 0);
-  const int oz = mz < 0 ? -1 : (mz >= C::S ? 1 : 0);
-  const int npx = a.npx;
-  const int pz = q / (npx * npx);
-  const int py = (q / npx) % npx;
-  const int px = q % npx;
-  const int qn = (px + ox + npx) % npx + npx * ((py + oy + npx) % npx) + npx * npx * ((pz + oz + npx) % npx);
-  const float* h = static_cast<const float*>(a.halo_in) + (size_t)qn * C::HALO;
-  const int nout = (ox != 0) + (oy != 0) + (oz != 0);
-  if (nout == 1) {
-    // a face: axis ax, the other two coordinates (u, v) in increasing axis order
-    const int ax = ox ? 0 : (oy ? 1 : 2);
-    const int u = ax == 0 ? my : mx;
-    const int v = ax == 2 ? my : mz;
-    const int c = ax == 0 ? cf[0] : (ax == 1 ? cf[1] : cf[2]);
-    const int k = ax == 0 ? sl[0] : (ax == 1 ? sl[1] : sl[2]);
-    return h[(size_t)(2 * ax + (c > 0 ? 1 : 0)) * C::FACE + (size_t)k * C::S2 + u + C::S * v];
-  }
-  // an edge: the axis pair off the tile and the coordinate along the third axis
-  const int pr = oz == 0 ? 0 : (oy == 0 ? 1 : 2);
-  const int ca = pr == 2 ? cf[1] : cf[0];
-  const int cb = pr == 0 ? cf[1] : cf[2];
-  const int w = pr == 0 ? mz : (pr == 1 ? my : mx);
-  const int e = 4 * pr + (ca > 0 ? 1 : 0) + 2 * (cb > 0 ? 1 : 0);
-  return h[6 * (size_t)C::FACE + (size_t)e * C::S + w];
+// Patch coordinates of q and of its neighbour at offset (ox, oy, oz), periodic.
+__device__ __forceinline__ int neighbour(int px, int py, int pz, int ox, int oy, int oz, int npx) {
+  int x = px + ox, y = py + oy, z = pz + oz;
+  x += x < 0 ? npx : (x >= npx ? -npx : 0);
+  y += y < 0 ? npx : (y >= npx ? -npx : 0);
+  z += z < 0 ? npx : (z >= npx ? -npx : 0);
+  return x + npx * (y + npx * z);
 }
 
-// S3 + streaming: f^in_f(n) = f_f(n - c_f) into scratch, from the LDS tile or
-// the neighbours' halo.
+// S3 + streaming: f^in_f(n) = f_f(n - c_f) into scratch.  Nodes whose source
+// lies in the tile copy it from LDS; the others (the planes n_a = 0 or S - 1
+// of the axes along which c_f points) read it from the neighbours' halo,
+// one independent load per node.
 template <class C, class SM>
 __device__ void stream_field(const PatchArgs& a, int q, int f, float* scr, SM& sm) {
   int cf[3] = {0, 0, 0}, sl[3] = {0, 0, 0};
@@ -403,46 +491,133 @@ __device__ void stream_field(const PatchArgs& a, int q, int f, float* scr, SM& s
     const int y = r / C::S;
     const int x = r - y * C::S;
     const int mx = x - cf[0], my = y - cf[1], mz = z - cf[2];
-    const bool in = (unsigned)mx < (unsigned)C::S && (unsigned)my < (unsigned)C::S && (unsigned)mz < (unsigned)C::S;
-    dst[t] = in ? sm.tile[t - shift] : halo_value<C>(a, q, cf, sl, mx, my, mz);
+    if ((unsigned)mx < (unsigned)C::S && (unsigned)my < (unsigned)C::S && (unsigned)mz < (unsigned)C::S)
+      dst[t] = sm.tile[t - shift];
+  }
+  const int npx = a.npx;
+  const int pz = q / (npx * npx), py = (q / npx) % npx, px = q % npx;
+  const float* halo = static_cast<const float*>(a.halo_in);
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (cf[ax] == 0) continue;
+    // receiving plane n_ax = 0 (c > 0) or S - 1 (c < 0); (u, v) over the
+    // other two axes b1 < b2
+    const int b1 = ax == 0 ? 1 : 0;
+    const int b2 = ax == 2 ? 1 : 2;
+    const int c1 = b1 == 0 ? cf[0] : cf[1];
+    const int c2 = b2 == 1 ? cf[1] : cf[2];
+    const int na = cf[ax] > 0 ? 0 : C::S - 1;
+    const int o = cf[ax] > 0 ? -1 : 1;   // neighbour offset along ax
+    const int s_ax = ax == 0 ? 1 : (ax == 1 ? C::S : C::S2);
+    const int s_1 = b1 == 0 ? 1 : C::S;
+    const int s_2 = b2 == 1 ? C::S : C::S2;
+    for (int i = threadIdx.x; i < C::S2; i += C::NT) {
+      const int v = i / C::S;
+      const int u = i - v * C::S;
+      const int m1 = u - c1, m2 = v - c2;
+      const int o1 = m1 < 0 ? -1 : (m1 >= C::S ? 1 : 0);
+      const int o2 = m2 < 0 ? -1 : (m2 >= C::S ? 1 : 0);
+      float val;
+      if (o1 == 0 && o2 == 0) {
+        // a face of the neighbour along ax
+        const int qn = neighbour(px, py, pz, ax == 0 ? o : 0, ax == 1 ? o : 0, ax == 2 ? o : 0, npx);
+        val = halo[(size_t)qn * C::HALO + (size_t)(2 * ax + (cf[ax] > 0 ? 1 : 0)) * C::FACE +
+                   (size_t)(ax == 0 ? sl[0] : (ax == 1 ? sl[1] : sl[2])) * C::S2 + m1 + C::S * m2];
+      } else {
+        // off the tile along ax and one more axis b: an edge line, taken by
+        // the plane of the smaller of the two axes
+        const int b = o1 != 0 ? b1 : b2;
+        if (b < ax) continue;
+        const int ob = o1 != 0 ? o1 : o2;
+        const int oxx = (ax == 0 ? o : 0) + (b == 0 ? ob : 0);
+        const int oyy = (ax == 1 ? o : 0) + (b == 1 ? ob : 0);
+        const int ozz = (ax == 2 ? o : 0) + (b == 2 ? ob : 0);
+        const int qn = neighbour(px, py, pz, oxx, oyy, ozz, npx);
+        // pair (x,y), (x,z) or (y,z) and the coordinate along the third axis
+        const int lo = ax < b ? ax : b, hi = ax < b ? b : ax;
+        const int pr = (lo == 0 && hi == 1) ? 0 : (lo == 0 ? 1 : 2);
+        const int ca = lo == 0 ? cf[0] : cf[1];
+        const int cb = hi == 1 ? cf[1] : cf[2];
+        const int w = o1 != 0 ? m2 : m1;   // the in-range coordinate
+        const int e = 4 * pr + (ca > 0 ? 1 : 0) + 2 * (cb > 0 ? 1 : 0);
+        val = halo[(size_t)qn * C::HALO + 6 * (size_t)C::FACE + (size_t)e * C::S + w];
+      }
+      dst[na * s_ax + u * s_1 + v * s_2] = val;
+    }
   }
 }
 
-// S4: BGK collision of every node of the patch in scratch (in place).
+// S4: BGK collision of every node of the patch in scratch (in place), two
+// nodes per thread and iteration so that 38 loads are in flight.
+template <class C>
+__device__ __forceinline__ void collide_node(float* fi, float om) {
+  float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    rho += fi[i];
+    if (D3Q19L::C[i][0]) jx += D3Q19L::C[i][0] > 0 ? fi[i] : -fi[i];
+    if (D3Q19L::C[i][1]) jy += D3Q19L::C[i][1] > 0 ? fi[i] : -fi[i];
+    if (D3Q19L::C[i][2]) jz += D3Q19L::C[i][2] > 0 ? fi[i] : -fi[i];
+  }
+  const float ux = jx / rho, uy = jy / rho, uz = jz / rho;
+  const float usq = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const float w = i == 0 ? (1.f / 3.f) : (i < 7 ? (1.f / 18.f) : (1.f / 36.f));
+    const float cu = (float)D3Q19L::C[i][0] * ux + (float)D3Q19L::C[i][1] * uy + (float)D3Q19L::C[i][2] * uz;
+    const float feq = w * rho * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * usq);
+    fi[i] = fi[i] - om * (fi[i] - feq);
+  }
+}
+
 template <class C>
 __device__ void collide(const PatchArgs& a, float* scr) {
   const float om = (float)a.omega;
-  for (int t = threadIdx.x; t < C::S3; t += C::NT) {
-    float fi[19];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) fi[i] = scr[(size_t)i * C::S3 + t];
-    float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+  for (int t0 = threadIdx.x; t0 < C::S3; t0 += 2 * C::NT) {
+    const int t1 = t0 + C::NT;
+    const bool two = t1 < C::S3;
+    float f0[19], f1[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-      rho += fi[i];
-      if (D3Q19L::C[i][0]) jx += D3Q19L::C[i][0] > 0 ? fi[i] : -fi[i];
-      if (D3Q19L::C[i][1]) jy += D3Q19L::C[i][1] > 0 ? fi[i] : -fi[i];
-      if (D3Q19L::C[i][2]) jz += D3Q19L::C[i][2] > 0 ? fi[i] : -fi[i];
+      f0[i] = scr[(size_t)i * C::S3 + t0];
+      f1[i] = two ? scr[(size_t)i * C::S3 + t1] : 1.f;
     }
-    const float ux = jx / rho, uy = jy / rho, uz = jz / rho;
-    const float usq = ux * ux + uy * uy + uz * uz;
+    collide_node<C>(f0, om);
+    collide_node<C>(f1, om);
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-      const float w = i == 0 ? (1.f / 3.f) : (i < 7 ? (1.f / 18.f) : (1.f / 36.f));
-      const float cu = (float)D3Q19L::C[i][0] * ux + (float)D3Q19L::C[i][1] * uy + (float)D3Q19L::C[i][2] * uz;
-      const float feq = w * rho * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * usq);
-      scr[(size_t)i * C::S3 + t] = fi[i] - om * (fi[i] - feq);
+      scr[(size_t)i * C::S3 + t0] = f0[i];
+      if (two) scr[(size_t)i * C::S3 + t1] = f1[i];
     }
   }
 }
 
-// C: from a transformed-or-not tile in LDS to the record, totals and export.
+// A field of scratch into the LDS tile, 12 loads in flight per thread.
 template <class C, class SM>
+__device__ void load_field(const float* src, SM& sm) {
+  constexpr int U = 12;
+  for (int t0 = threadIdx.x; t0 < C::S3; t0 += U * C::NT) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * C::NT;
+      v[u] = t < C::S3 ? src[t] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * C::NT;
+      if (t < C::S3) sm.tile[t] = v[u];
+    }
+  }
+  __syncthreads();
+}
+
+// C: from a transformed-or-not tile in LDS to the record, totals and export.
+template <class C, bool THR, class SM>
 __device__ void finish_field(const PatchArgs& a, int q, int f, SM& sm) {
-  compact_field<C>(a, q, f, sm);
-  __syncthreads();   // the record stores read the tile
+  compact_field<C, THR>(a, q, f, sm);
+  total_field<C, true>(a, q, f, sm);   // its barrier also ends the record stores' tile reads
   inverse3<C>(sm.tile, a.levels);
-  total_field<C, true>(a, q, f, sm);
   export_field<C>(a, q, f, sm);
   __syncthreads();
 }
@@ -450,20 +625,33 @@ __device__ void finish_field(const PatchArgs& a, int q, int f, SM& sm) {
 template <class C, class SM>
 __device__ void step_patch(const PatchArgs& a, int q, float* scr, SM& sm) {
   const int L = a.levels;
+  P3_START();
   for (int f = 0; f < C::M; ++f) {
     expand_field<C>(a, q, f, sm);
+    P3_MARK(0);
     inverse3<C>(sm.tile, L);
+    P3_MARK(1);
     stream_field<C>(a, q, f, scr, sm);
     __syncthreads();
+    P3_MARK(2);
   }
   collide<C>(a, scr);
   __syncthreads();
+  P3_MARK(3);
   for (int f = 0; f < C::M; ++f) {
-    const float* src = scr + (size_t)f * C::S3;
-    for (int t = threadIdx.x; t < C::S3; t += C::NT) sm.tile[t] = src[t];
+    load_field<C>(scr + (size_t)f * C::S3, sm);
+    P3_MARK(4);
+    forward3_threshold<C>(a, sm.tile);
+    P3_MARK(5);
+    compact_field<C, false>(a, q, f, sm);
+    P3_MARK(6);
+    total_field<C, true>(a, q, f, sm);
+    P3_MARK(7);
+    inverse3<C>(sm.tile, a.levels);
+    P3_MARK(8);
+    export_field<C>(a, q, f, sm);
     __syncthreads();
-    forward3<C>(sm.tile, L);
-    finish_field<C>(a, q, f, sm);
+    P3_MARK(9);
   }
 }
 
@@ -506,18 +694,18 @@ __global__ __launch_bounds__(1024) void d3q19_aux_kernel(PatchArgs a) {
         sm.tile[t] = src[((size_t)gz * n + gy) * n + gx];
       }
       __syncthreads();
-      forward3<C>(sm.tile, a.levels);
-      finish_field<C>(a, q, f, sm);
+      forward3_threshold<C>(a, sm.tile);
+      finish_field<C, false>(a, q, f, sm);
     } else if (a.mode == AUX_COEF) {
       const float* src = static_cast<const float*>(a.coef_in) + ((size_t)q * C::M + f) * C::S3;
       for (int t = threadIdx.x; t < C::S3; t += C::NT) sm.tile[t] = src[t];
       __syncthreads();
-      finish_field<C>(a, q, f, sm);
+      finish_field<C, true>(a, q, f, sm);
     } else {
       expand_field<C>(a, q, f, sm);
+      if (a.mode == AUX_RESTORE) total_field<C, false>(a, q, f, sm);
       inverse3<C>(sm.tile, a.levels);
       if (a.mode == AUX_RESTORE) {
-        total_field<C, false>(a, q, f, sm);
         export_field<C>(a, q, f, sm);
       } else {
         float* dst = static_cast<float*>(a.dense_out) + (size_t)f * n * n * n;
@@ -634,6 +822,13 @@ static void d3q19_case(int op, const PatchArgs* a, int grid, hipStream_t s, hipE
       *err = hipErrorInvalidValue;
   }
 }
+
+#ifdef LBMZ_PHASE_CLOCK
+extern "C" int lbmz_debug_phase3(void* host, size_t bytes) {
+  if (bytes > sizeof(lbmz_phase3)) bytes = sizeof(lbmz_phase3);
+  return hipMemcpyFromSymbol(host, HIP_SYMBOL(lbmz_phase3), bytes, 0, hipMemcpyDeviceToHost) == hipSuccess ? 0 : -3;
+}
+#endif
 
 bool dispatch_f32_d3q19(LBMZ_DISPATCH_ARGS) {
   if (k.dtype != 0 || k.scheme != S_LBM3 || k.wavelet != W_BL53 || k.vf != VF_F32) return false;

@@ -56,7 +56,7 @@ def _tiles(ctx):
     return decode_records3(table, pool, ctx.s), table, pool
 
 
-@pytest.mark.parametrize("n,p,levels", [(32, 16, 3), (64, 32, 3)])
+@pytest.mark.parametrize("n,p,levels", [(32, 16, 3), (64, 32, 3), (32, 16, 0), (32, 16, 1)])
 def test_setup_and_decompression(n, p, levels):
     _say("3d setup", n, p, levels)
     ctx = _ctx(n, p, levels, 0.0)
@@ -120,7 +120,8 @@ def test_records_from_given_coefficients_are_the_oracles(density):
         assert st["mask_records"] > 0
 
 
-@pytest.mark.parametrize("n,p,levels,eps", [(48, 16, 3, 1e-4), (64, 32, 3, 1e-4), (32, 16, 2, 1e-3)])
+@pytest.mark.parametrize("n,p,levels,eps", [(48, 16, 3, 1e-4), (64, 32, 3, 1e-4), (32, 16, 2, 1e-3),
+                                             (32, 16, 1, 1e-3)])
 def test_one_step_from_common_state(n, p, levels, eps):
     _say("3d one step", n, p, levels, eps)
     g = O3.Geometry3(n, p, levels)
@@ -207,3 +208,50 @@ def test_invalid_3d_configurations_are_rejected():
     ctx = _ctx(32, 16, 3, 1e-4)
     with pytest.raises(LbmzError):
         ctx.set_patch_eps(np.full(8, 1e-4))
+
+
+def test_full_size_sampled_patches():
+    """768^3, 32^3 patches, L = 3 (the measured workload, same launch): one GPU
+    step of sampled patches against the oracle's step of the same patches,
+    computed from the GPU's own store (the neighbours' records decoded and
+    rebuilt on the host)."""
+    _say("3d full size sampled")
+    n, p, levels, eps = 768, 32, 3, 1e-4
+    g = O3.Geometry3(n, p, levels)
+    ctx = _ctx(n, p, levels, eps)
+    macro = taylor_green_jets_3d(n, seed=0, dtype=np.float32)
+    ctx.set_macroscopic(*macro)
+    del macro
+    ctx.step(2)
+    table, pool = ctx.store()
+    thr = O3.threshold_table3(g.s, levels, eps, "capped", np.float32)
+    cache = {}
+
+    def lossy(k):
+        if k not in cache:
+            c = np.stack([O3.decode_record3(pool, int(table[k, f, 0]), int(table[k, f, 1]), g.s, np.float32)
+                          for f in range(19)])
+            cache[k] = O3.inverse_3d(c, levels)
+        return cache[k]
+
+    npx = g.npx
+    samples = [0, g.npatch - 1, (npx // 2) + npx * (npx // 3) + npx * npx * (npx - 2)]
+    want = {}
+    for q in samples:
+        padded = O3.gather_ghosts3_one(lossy, g, q)
+        new = O3.d3q19_bgk_update(padded, TAU).astype(np.float32)
+        want[q] = O3.hard_threshold(O3.forward_3d(new, levels), thr)
+    ctx.step(1)
+    table2, pool2 = ctx.store()
+    u = np.finfo(np.float32).eps
+    for q in samples:
+        got = np.stack([O3.decode_record3(pool2, int(table2[q, f, 0]), int(table2[q, f, 1]), g.s, np.float32)
+                        for f in range(19)])
+        w = want[q]
+        delta = 256 * u * float(np.max(np.abs(w)))
+        flip = (got != 0) != (w != 0)
+        near = np.abs(np.abs(np.where(got != 0, got, w)) - thr) <= delta
+        assert np.all(near[flip]), (q, int(flip.sum()))
+        assert np.max(np.abs(np.where(flip, 0.0, got - w))) <= delta, q
+        assert 0 < np.count_nonzero(got) < got.size
+    assert ctx.stats()["regrows"] >= 0
