@@ -71,7 +71,8 @@ def halo_bytes(npatch: int) -> int:
     return npatch * 4 * 3 * (P + 1) * 4
 
 
-KERNEL_SOURCES = ["paper_2302_09883_amd/csrc/lbmz_patch_kernel.h", "paper_2302_09883_amd/csrc/lbmz_inst_f32_lbm.hip"]
+KERNEL_SOURCES = ["paper_2302_09883_amd/csrc/lbmz_patch_kernel.h", "paper_2302_09883_amd/csrc/lbmz_internal.h",
+                  "paper_2302_09883_amd/csrc/lbmz_inst_f32_lbm.hip"]
 TRAFFIC_FILE = "profiles/traffic_patch_step_d2q9_2048_eps1e-4.txt"
 
 
