@@ -64,6 +64,7 @@ struct Cfg3 {
   static constexpr int LMAX = ilog2c(P) - 1;
   static constexpr int FACE = 5 * S2;
   static constexpr int HALO = 6 * FACE + 12 * S;
+  static constexpr int SF = (S3 + 3) & ~3;   // scratch floats per field (16-byte aligned slices)
   static_assert(W <= NT, "one scan entry per thread");
   static_assert(S3 < 65536, "u16 indices");
 };
@@ -484,7 +485,7 @@ __device__ void stream_field(const PatchArgs& a, int q, int f, float* scr, SM& s
       sl[2] = D3Q19L::slot(i, 2);
     }
   const int shift = cf[0] + C::S * cf[1] + C::S2 * cf[2];
-  float* dst = scr + (size_t)f * C::S3;
+  float* dst = scr + (size_t)f * C::SF;
   for (int t = threadIdx.x; t < C::S3; t += C::NT) {
     const int z = t / C::S2;
     const int r = t - z * C::S2;
@@ -547,8 +548,7 @@ __device__ void stream_field(const PatchArgs& a, int q, int f, float* scr, SM& s
   }
 }
 
-// S4: BGK collision of every node of the patch in scratch (in place), two
-// nodes per thread and iteration so that 38 loads are in flight.
+// S4: BGK collision of every node of the patch in scratch (in place).
 template <class C>
 __device__ __forceinline__ void collide_node(float* fi, float om) {
   float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
@@ -573,40 +573,46 @@ __device__ __forceinline__ void collide_node(float* fi, float om) {
 template <class C>
 __device__ void collide(const PatchArgs& a, float* scr) {
   const float om = (float)a.omega;
-  for (int t0 = threadIdx.x; t0 < C::S3; t0 += 2 * C::NT) {
-    const int t1 = t0 + C::NT;
-    const bool two = t1 < C::S3;
-    float f0[19], f1[19];
+  // two consecutive nodes per thread and iteration: 19 8-byte loads in flight
+  for (int i2 = threadIdx.x; i2 < C::SF / 2; i2 += C::NT) {
+    float2 q[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      f0[i] = scr[(size_t)i * C::S3 + t0];
-      f1[i] = two ? scr[(size_t)i * C::S3 + t1] : 1.f;
-    }
-    collide_node<C>(f0, om);
-    collide_node<C>(f1, om);
+    for (int i = 0; i < 19; ++i) q[i] = reinterpret_cast<const float2*>(scr + (size_t)i * C::SF)[i2];
+    float f[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      scr[(size_t)i * C::S3 + t0] = f0[i];
-      if (two) scr[(size_t)i * C::S3 + t1] = f1[i];
-    }
+    for (int i = 0; i < 19; ++i) f[i] = q[i].x;
+    collide_node<C>(f, om);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) q[i].x = f[i];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) f[i] = q[i].y;
+    collide_node<C>(f, om);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) q[i].y = f[i];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) reinterpret_cast<float2*>(scr + (size_t)i * C::SF)[i2] = q[i];
   }
 }
 
-// A field of scratch into the LDS tile, 12 loads in flight per thread.
+// A field of scratch into the LDS tile, 16-byte loads, three in flight per thread.
 template <class C, class SM>
 __device__ void load_field(const float* src, SM& sm) {
-  constexpr int U = 12;
-  for (int t0 = threadIdx.x; t0 < C::S3; t0 += U * C::NT) {
-    float v[U];
+  constexpr int U = 3;
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  for (int i0 = threadIdx.x; i0 < C::SF / 4; i0 += U * C::NT) {
+    float4 v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * C::NT;
-      v[u] = t < C::S3 ? src[t] : 0.f;
+      const int i4 = i0 + u * C::NT;
+      v[u] = i4 < C::SF / 4 ? s4[i4] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * C::NT;
-      if (t < C::S3) sm.tile[t] = v[u];
+      const int t = 4 * (i0 + u * C::NT);
+      if (t + 0 < C::S3) sm.tile[t + 0] = v[u].x;
+      if (t + 1 < C::S3) sm.tile[t + 1] = v[u].y;
+      if (t + 2 < C::S3) sm.tile[t + 2] = v[u].z;
+      if (t + 3 < C::S3) sm.tile[t + 3] = v[u].w;
     }
   }
   __syncthreads();
@@ -639,7 +645,7 @@ __device__ void step_patch(const PatchArgs& a, int q, float* scr, SM& sm) {
   __syncthreads();
   P3_MARK(3);
   for (int f = 0; f < C::M; ++f) {
-    load_field<C>(scr + (size_t)f * C::S3, sm);
+    load_field<C>(scr + (size_t)f * C::SF, sm);
     P3_MARK(4);
     forward3_threshold<C>(a, sm.tile);
     P3_MARK(5);
@@ -662,7 +668,7 @@ __global__ __launch_bounds__(1024) void d3q19_step_kernel(PatchArgs a) {
   using C = Cfg3<P>;
   __shared__ Smem3<C> sm;
   if (step_stops(a, blockIdx.x == 0, sm)) return;
-  float* scr = a.scratch + (size_t)blockIdx.x * C::M * C::S3;
+  float* scr = a.scratch + (size_t)blockIdx.x * C::M * C::SF;
   for (;;) {
     if (threadIdx.x == 0) sm.misc[3] = atomicAdd(&a.ctrl->queue[a.epoch % 3u], 1u);
     __syncthreads();
@@ -816,7 +822,7 @@ static void d3q19_case(int op, const PatchArgs* a, int grid, hipStream_t s, hipE
       *out = (size_t)C::HALO;
       break;
     case 8:   // scratch floats per workgroup
-      *out = (size_t)C::M * C::S3;
+      *out = (size_t)C::M * C::SF;
       break;
     default:
       *err = hipErrorInvalidValue;
