@@ -255,3 +255,40 @@ def test_full_size_sampled_patches():
         assert np.max(np.abs(np.where(flip, 0.0, got - w))) <= delta, q
         assert 0 < np.count_nonzero(got) < got.size
     assert ctx.stats()["regrows"] >= 0
+
+
+def test_single_patch_grid_is_its_own_neighbour():
+    """n = p: every halo plane and line comes from the patch itself (periodic)."""
+    _say("3d single patch")
+    n, p, levels, eps = 16, 16, 3, 1e-3
+    g = O3.Geometry3(n, p, levels)
+    twin = O3.CompressedRun3(g, TAU, eps, dtype=np.float32)
+    twin.set_grid(_oracle_state(n, 7, np.float32))
+    table, pool = twin.store()
+    ctx = _ctx(n, p, levels, eps)
+    ctx.put_store(table, pool)
+    ctx.step(1)
+    twin.step(1)
+    got, _, _ = _tiles(ctx)
+    want = twin.coef
+    delta = 256 * np.finfo(np.float32).eps * float(np.max(np.abs(want)))
+    flip = (got != 0) != (want != 0)
+    near = np.abs(np.abs(np.where(got != 0, got, want)) - twin.thr) <= delta
+    assert np.all(near[flip])
+    assert np.max(np.abs(np.where(flip, 0.0, got - want))) <= delta
+
+
+def test_set_field_per_population():
+    _say("3d set_field")
+    n, p, levels = 32, 16, 2
+    f0 = _oracle_state(n, 8, np.float32)
+    ctx = _ctx(n, p, levels, 0.0)
+    for i in range(19):
+        ctx.set_field(i, f0[i])
+    got = ctx.fields()
+    assert np.max(np.abs(got - f0)) <= 2e-6 * np.max(np.abs(f0))
+    ctx.step(2)
+    ref = f0.astype(np.float64)
+    for _ in range(2):
+        ref = O3.dense_step3(ref, TAU)
+    assert np.linalg.norm(ctx.fields() - ref) / np.linalg.norm(ref) <= 1e-5
