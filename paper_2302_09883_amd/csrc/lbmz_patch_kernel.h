@@ -861,8 +861,50 @@ __device__ __forceinline__ void prefetch_table(const PatchArgs& a, int q, SM& sm
 // Index-list records (sparse) are scattered into a zeroed LDS tile first.
 // With TOT, the S9 totals of the stored coefficients are taken on the way.
 
+// Entries of the patch's index-list records held by the helper waves (the
+// waves without a line in the passes) from the start of the patch until the
+// scatter of the expansion.
+template <class C, class T>
+struct ListRegs {
+  T lv[C::M][C::LPT];
+  int li[C::M][C::LPT];
+};
+
+// Issue the loads of patch q's index-list entries (helper waves; the offset
+// table is read from global memory so that the loads start before the barrier
+// that precedes the expansion).
+template <class C, class T>
+__device__ __forceinline__ void prefetch_lists(const PatchArgs& a, int q, ListRegs<C, T>& lr) {
+  const int wave = wave_id();
+  if (wave < C::NPASS) return;
+  const int ht = threadIdx.x - 64 * C::NPASS;
+  const uint32_t* tq = a.table_in + 2 * (size_t)q * C::M;
+#pragma unroll
+  for (int f = 0; f < C::M; ++f) {
+    const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)tq[2 * f + 1]);
+    const uint32_t nnz = w & ~MASK_BIT;
+#pragma unroll
+    for (int u = 0; u < C::LPT; ++u) {
+      lr.li[f][u] = -1;
+      lr.lv[f][u] = T(0);
+    }
+    if (!(w & MASK_BIT)) {
+      const uint8_t* rec = a.pool_in + 16ull * (uint32_t)__builtin_amdgcn_readfirstlane((int)tq[2 * f]);
+      const uint16_t* idx = reinterpret_cast<const uint16_t*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
+#pragma unroll
+      for (int u = 0; u < C::LPT; ++u) {
+        const int k = ht + u * C::NHT;
+        if (k < (int)nnz) {
+          lr.li[f][u] = idx[k];
+          lr.lv[f][u] = reinterpret_cast<const T*>(rec)[k];
+        }
+      }
+    }
+  }
+}
+
 template <class C, class T, int WAV, bool TOT, class SM>
-__device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm) {
+__device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm, const ListRegs<C, T>& lr) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -874,36 +916,15 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
   auto tel = [&sm](int i) { return sm.te[i]; };
   const uint8_t* pool = a.pool_in;
 
-  // Index-list records: the helper waves (no line in the passes) load their
-  // entries and zero their tiles, so that the line waves carry no list state.
+  // Index-list records: the helper waves (no line in the passes) hold their
+  // entries (prefetch_lists) and zero their tiles, so that the line waves
+  // carry no list state.
   const bool helper = wave >= C::NPASS;
   const int ht = tid - 64 * C::NPASS;
-  T lv[C::M][C::LPT];
-  int li[C::M][C::LPT];
   if (helper) {
 #pragma unroll
-    for (int f = 0; f < C::M; ++f) {
-      const uint32_t w = te(2 * f + 1);
-      const uint32_t nnz = w & ~MASK_BIT;
-#pragma unroll
-      for (int u = 0; u < C::LPT; ++u) {
-        li[f][u] = -1;
-        lv[f][u] = T(0);
-      }
-      if (!(w & MASK_BIT)) {
-        const uint8_t* rec = pool + 16ull * te(2 * f);
-        const uint16_t* idx = reinterpret_cast<const uint16_t*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
-#pragma unroll
-        for (int u = 0; u < C::LPT; ++u) {
-          const int k = ht + u * C::NHT;
-          if (k < (int)nnz) {
-            li[f][u] = idx[k];
-            lv[f][u] = reinterpret_cast<const T*>(rec)[k];
-          }
-        }
-        zero_span<T>(sm.tile + C::Lay::fb(f), C::S * C::RS, ht, C::NHT);
-      }
-    }
+    for (int f = 0; f < C::M; ++f)
+      if (!(te(2 * f + 1) & MASK_BIT)) zero_span<T>(sm.tile + C::Lay::fb(f), C::S * C::RS, ht, C::NHT);
   }
 
   // Bitmask records, owned columns (waves 0..M-1).
@@ -986,11 +1007,11 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
     for (int f = 0; f < C::M; ++f) {
 #pragma unroll
       for (int u = 0; u < C::LPT; ++u) {
-        const int k = li[f][u];
+        const int k = lr.li[f][u];
         if (k >= 0 && k < C::NC) {
           int x, y;
           record_node<C>(k, x, y);
-          sm.tile[C::Lay::fb(f) + y * C::RS + x] = lv[f][u];
+          sm.tile[C::Lay::fb(f) + y * C::RS + x] = lr.lv[f][u];
         }
       }
     }
@@ -1244,8 +1265,8 @@ namespace lbmz {
 // ---------------------------------------------------------------------------
 
 template <class C, class T, int WAV, bool TOT, int VF, class SM>
-__device__ __forceinline__ void expand_any(const PatchArgs& a, int q, SM& sm) {
-  if constexpr (VF == VF_F32) expand_columns<C, T, WAV, TOT>(a, q, sm);
+__device__ __forceinline__ void expand_any(const PatchArgs& a, int q, SM& sm, const ListRegs<C, T>& lr) {
+  if constexpr (VF == VF_F32) expand_columns<C, T, WAV, TOT>(a, q, sm, lr);
   else expand_columns_q<C, T, WAV, TOT, VF>(a, q, sm);
 }
 
@@ -1256,9 +1277,11 @@ __device__ __forceinline__ bool compact_any(const PatchArgs& a, int q, SM& sm) {
 }
 
 // The loads that start a patch, issued before the barrier that precedes the
-// expansion: the ghost values (S3) and the offset-table entries.
-template <class C, class T, int SCH, class SM>
-__device__ __forceinline__ void begin_patch(const PatchArgs& a, int q, SM& sm) {
+// expansion: the index-list entries (float32 records), the ghost values (S3)
+// and the offset-table entries.
+template <class C, class T, int SCH, int VF, class SM>
+__device__ __forceinline__ void begin_patch(const PatchArgs& a, int q, SM& sm, ListRegs<C, T>& lr) {
+  if constexpr (VF == VF_F32) prefetch_lists<C, T>(a, q, lr);
   prefetch_table<C>(a, q, sm);
   if constexpr (SCH == S_LBM) gather_lbm<C, T>(a, q, sm.tile, sm.ghost);
   else gather_fv<C, T>(a, q, sm.ghost);
@@ -1266,10 +1289,10 @@ __device__ __forceinline__ void begin_patch(const PatchArgs& a, int q, SM& sm) {
 
 // One step (time n -> n + 1) of patch q, S1..S9, after begin_patch and a barrier.
 template <class C, class T, int WAV, int SCH, int VF, class SM>
-__device__ __forceinline__ void step_one_patch(const PatchArgs& a, int q, SM& sm) {
+__device__ __forceinline__ void step_one_patch(const PatchArgs& a, int q, SM& sm, const ListRegs<C, T>& lr) {
   LBMZ_MARK(0);
   LBMZ_MARK(14);
-  expand_any<C, T, WAV, false, VF>(a, q, sm);
+  expand_any<C, T, WAV, false, VF>(a, q, sm, lr);
   LBMZ_MARK(1);
   row_pass<C, T, WAV, SCH, SCH == S_LBM ? ROW_INV_SHIFT : ROW_INV>(a, q, sm.tile, sm.ghost);
   __syncthreads();
@@ -1311,9 +1334,10 @@ template <class T, int P, int WAV, int SCH, int VF = VF_F32>
 __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(PatchArgs a) {
   using C = Cfg<T, P, WAV, SCH>;
   __shared__ Smem<C, T, VF> sm;
-  begin_patch<C, T, SCH>(a, blockIdx.x, sm);
+  ListRegs<C, T> lr;
+  begin_patch<C, T, SCH, VF>(a, blockIdx.x, sm, lr);
   if (step_stops(a, blockIdx.x == 0, sm)) return;
-  step_one_patch<C, T, WAV, SCH, VF>(a, blockIdx.x, sm);
+  step_one_patch<C, T, WAV, SCH, VF>(a, blockIdx.x, sm, lr);
 }
 
 // One step of every patch by a fixed set of resident workgroups that take
@@ -1328,9 +1352,10 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_persiste
     __syncthreads();
     const int q = (int)sm.misc[3];
     if (q >= a.npatch) break;
-    begin_patch<C, T, SCH>(a, q, sm);
+    ListRegs<C, T> lr;
+    begin_patch<C, T, SCH, VF>(a, q, sm, lr);
     __syncthreads();
-    step_one_patch<C, T, WAV, SCH, VF>(a, q, sm);
+    step_one_patch<C, T, WAV, SCH, VF>(a, q, sm, lr);
     __syncthreads();
   }
 }
@@ -1373,14 +1398,16 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
     row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
     return;
   }
+  ListRegs<C, T> lr;
+  if constexpr (VF == VF_F32) prefetch_lists<C, T>(a, q, lr);
   prefetch_table<C>(a, q, sm);
   __syncthreads();
   if (a.mode == AUX_RESTORE) {
-    expand_any<C, T, WAV, true, VF>(a, q, sm);
+    expand_any<C, T, WAV, true, VF>(a, q, sm, lr);
     totals_finish<C, T, false>(a, a.partials_out + (size_t)q * C::M, a.levels, sm);
     row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
   } else {
-    expand_any<C, T, WAV, false, VF>(a, q, sm);
+    expand_any<C, T, WAV, false, VF>(a, q, sm, lr);
     row_pass<C, T, WAV, SCH, ROW_INV_DENSE>(a, q, sm.tile, sm.ghost);
   }
 }
