@@ -267,8 +267,10 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
     float v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      // clamped address, so that the reads are unconditional and overlap
       const int t = 64 * (c0 + u * C::NW) + lane;
-      v[u] = t < C::S3 ? sm.tile[t] : 0.f;
+      const float r = sm.tile[t < C::S3 ? t : C::S3 - 1];
+      v[u] = t < C::S3 ? r : 0.f;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -335,8 +337,10 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
     for (int u = 0; u < U; ++u) {
       const int c = c0 + u * C::NW;
       const int t = 64 * c + lane;
-      v[u] = t < C::S3 ? sm.tile[t] : 0.f;
-      pre[u] = c < C::W ? sm.pre[c] : 0u;
+      const float r = sm.tile[t < C::S3 ? t : C::S3 - 1];
+      const uint32_t p = sm.pre[c < C::W ? c : C::W - 1];
+      v[u] = t < C::S3 ? r : 0.f;
+      pre[u] = c < C::W ? p : 0u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -486,14 +490,27 @@ __device__ void stream_field(const PatchArgs& a, int q, int f, float* scr, SM& s
     }
   const int shift = cf[0] + C::S * cf[1] + C::S2 * cf[2];
   float* dst = scr + (size_t)f * C::SF;
-  for (int t = threadIdx.x; t < C::S3; t += C::NT) {
-    const int z = t / C::S2;
-    const int r = t - z * C::S2;
-    const int y = r / C::S;
-    const int x = r - y * C::S;
-    const int mx = x - cf[0], my = y - cf[1], mz = z - cf[2];
-    if ((unsigned)mx < (unsigned)C::S && (unsigned)my < (unsigned)C::S && (unsigned)mz < (unsigned)C::S)
-      dst[t] = sm.tile[t - shift];
+  constexpr int U = 4;   // nodes per thread and iteration (independent LDS reads in flight)
+  for (int t0 = threadIdx.x; t0 < C::S3; t0 += U * C::NT) {
+    float val[U];
+    bool in[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * C::NT;
+      const int z = t / C::S2;
+      const int r = t - z * C::S2;
+      const int y = r / C::S;
+      const int x = r - y * C::S;
+      const int mx = x - cf[0], my = y - cf[1], mz = z - cf[2];
+      in[u] = t < C::S3 && (unsigned)mx < (unsigned)C::S && (unsigned)my < (unsigned)C::S &&
+              (unsigned)mz < (unsigned)C::S;
+      // clamped address: the read is unconditional, the store is not
+      const int src = t - shift;
+      val[u] = sm.tile[src < 0 ? 0 : (src >= C::S3 ? C::S3 - 1 : src)];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (in[u]) dst[t0 + u * C::NT] = val[u];
   }
   const int npx = a.npx;
   const int pz = q / (npx * npx), py = (q / npx) % npx, px = q % npx;
