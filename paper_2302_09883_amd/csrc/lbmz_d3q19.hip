@@ -706,6 +706,7 @@ __global__ __launch_bounds__(1024) void d3q19_aux_kernel(PatchArgs a) {
   const int npx = a.npx;
   const int pz = q / (npx * npx), py = (q / npx) % npx, px = q % npx;
   for (int f = 0; f < C::M; ++f) {
+    if (a.mode == AUX_DECOMP && a.field_only >= 0 && f != a.field_only) continue;
     if (a.mode == AUX_INIT) {
       const float* src = static_cast<const float*>(a.dense_in) + (size_t)f * n * n * n;
       for (int t = threadIdx.x; t < C::S3; t += C::NT) {
@@ -731,7 +732,7 @@ __global__ __launch_bounds__(1024) void d3q19_aux_kernel(PatchArgs a) {
       if (a.mode == AUX_RESTORE) {
         export_field<C>(a, q, f, sm);
       } else {
-        float* dst = static_cast<float*>(a.dense_out) + (size_t)f * n * n * n;
+        float* dst = static_cast<float*>(a.dense_out) + (a.field_only >= 0 ? 0 : (size_t)f * n * n * n);
         for (int t = threadIdx.x; t < C::P * C::P * C::P; t += C::NT) {
           const int z = t / (C::P * C::P);
           const int r = t - z * C::P * C::P;

@@ -68,6 +68,7 @@ struct PatchArgs {
   const void* dense_in;          // AUX_INIT: [nfields][n][n] ([nfields][n][n][n] in 3-D)
   const void* coef_in;           // AUX_COEF: [npatch][nfields][s][s] ([...][s][s][s] in 3-D)
   void* dense_out;               // AUX_DECOMP: same layout as dense_in
+  int field_only;                // AUX_DECOMP, 3-D: >= 0 decompresses that field alone into dense_out [n][n][n]
 };
 
 // Configuration key of a compiled kernel family.

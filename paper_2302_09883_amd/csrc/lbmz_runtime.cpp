@@ -374,11 +374,13 @@ int commit(lbmz_ctx* c) {
   return LBMZ_OK;
 }
 
-// Decompress every field of the current compressed state into dst [M][n][n].
-int decompress_all(lbmz_ctx* c, void* dst) {
+// Decompress every field of the current compressed state into dst [M][n][n]
+// (field_only >= 0, 3-D: that field alone into dst [n][n][n]).
+int decompress_all(lbmz_ctx* c, void* dst, int field_only = -1) {
   PatchArgs a = args_for(c, c->cur, c->cur, 0);
   a.mode = AUX_DECOMP;
   a.dense_out = dst;
+  a.field_only = field_only;
   HIPCHK(c, launch_aux(c->key, a, c->npatch, c->stream));
   return LBMZ_OK;
 }
@@ -445,6 +447,7 @@ int validate_common(const lbmz_grid* g, const lbmz_scheme* sc, lbmz_ctx* c) {
   c->nslot = c->scheme == S_LBM ? 3 : c->nfields;
   PatchArgs& a = c->base;
   memset(&a, 0, sizeof a);
+  a.field_only = -1;
   a.n = c->n;
   if (c->scheme == S_EULER) {
     a.dt_over_h = sc->cfl / sc->vel[0];
@@ -840,11 +843,15 @@ int lbmz_decompress_field(lbmz_ctx* c, int field, void* dst, size_t bytes, int d
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBMZ_OK;
   }
-  void* tmp = dalloc(c, dense_bytes(c));
+  // 3-D: the requested field alone (one n^3 buffer); 2-D: all fields (the
+  // expansion reads every record of a patch at once)
+  const bool one = c->dim == 3;
+  void* tmp = dalloc(c, one ? field_bytes(c) : dense_bytes(c));
   if (!tmp) return fail(c, LBMZ_ENOMEM, "decompression scratch allocation failed");
-  rc = decompress_all(c, tmp);
+  rc = decompress_all(c, tmp, one ? field : -1);
   if (!rc) {
-    hipError_t e = hipMemcpyAsync(dst, static_cast<uint8_t*>(tmp) + field * field_bytes(c), bytes, kind, c->stream);
+    hipError_t e = hipMemcpyAsync(dst, static_cast<uint8_t*>(tmp) + (one ? 0 : field * field_bytes(c)), bytes, kind,
+                                  c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) rc = fail(c, LBMZ_EDEVICE, "decompress copy: %s", hipGetErrorString(e));
   }
