@@ -57,13 +57,19 @@ def line_flops(s: int, levels: int) -> int:
 
 
 def flops_per_patch(p: int = P, levels: int = LEVELS, nfields: int = 9) -> int:
-    """Algorithmic FP32 flops of one patch step: three 2-D transforms (inverse,
-    forward, re-inverse) of every field plus the D2Q9 collision of every node
-    (126 flops: 18 for the moments, 9 for the velocity, 99 for the nine
-    equilibria and relaxations)."""
+    """Algorithmic FP32 flops of one patch step: the inverse (S2) and forward
+    (S5) 2-D transforms of every field; for the export (S8) the column half of
+    the re-inverse, the two edge values of every row of the 6 populations that
+    cross the x faces (7 flops per level: an update of two fused multiply-adds
+    and a predict of an add and a fused multiply-add) and the full inverse of
+    the 6 exported rows; plus the D2Q9 collision of every node (126 flops: 18
+    for the moments, 9 for the velocity, 99 for the nine equilibria and
+    relaxations)."""
     s = p + 1
-    transforms = 3 * nfields * 2 * s * line_flops(s, levels)
-    return transforms + 126 * s * s
+    lf = line_flops(s, levels)
+    transforms = 2 * nfields * 2 * s * lf + nfields * s * lf
+    export = 6 * s * 7 * levels + 6 * lf
+    return transforms + export + 126 * s * s
 
 
 def halo_bytes(npatch: int) -> int:

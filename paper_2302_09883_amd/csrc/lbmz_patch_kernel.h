@@ -637,6 +637,82 @@ __device__ __forceinline__ void row_pass(const PatchArgs& a, int q, T* tile, con
 }
 
 // ---------------------------------------------------------------------------
+// S8, row half, folded BL5/3: only what the neighbours read
+// ---------------------------------------------------------------------------
+// The x strips need each row's value at nodes LO = 1 and HI = P - 1 only.
+// The inverse of levels L..1 at node 1 depends on the coarse sample at 2^L,
+// the boundary node 0 and the details at 2^(lev-1) and 3 * 2^(lev-1) of each
+// level: per level one update of the sample at 2 * st (k = 1) and one
+// predict of the detail at st (k = 0), in the operation order of the full
+// inverse, so the value is the one the full inverse gives.  Node P - 1 is the
+// mirror image (update of k = m - 1, predict of k = m - 1).
+template <class C, class T, bool MIRROR>
+__device__ __forceinline__ T bl53_inv_edge(const T* row, int L) {
+  auto at = [row](int j) { return MIRROR ? row[C::S - 1 - j] : row[j]; };
+  T y = at(1 << L);
+#pragma unroll
+  for (int lev = C::LMAX; lev >= 1; --lev) {
+    if (lev > L) continue;
+    const int st = 1 << (lev - 1);
+    const int m = (C::S - 1) / (2 * st);
+    const T a1 = (m == 2) ? T(0.5) : T(0.25);
+    T e;
+    if constexpr (!MIRROR) e = (y - T(0.5) * at(st)) - a1 * at(3 * st);
+    else e = (y - a1 * at(3 * st)) - T(0.5) * at(st);
+    if constexpr (!MIRROR) y = at(st) + (at(0) + e) * T(0.5);
+    else y = at(st) + (e + at(0)) * T(0.5);
+  }
+  return y;
+}
+
+// Export of the lines the neighbours need (the tile holds the column-inverted
+// coefficients): the line waves compute the x strips' two values of their
+// rows; the helper waves invert the full rows LO and HI of the y strips.
+template <class C, class T, int SCH>
+__device__ __forceinline__ void export_rows_bl53(const PatchArgs& a, int q, const T* tile) {
+  using LF = Lift<T, C::S, W_BL53, 1, C::LMAX>;
+  static_assert(C::NHT >= 2 * C::M, "one helper thread per exported full row");
+  T* h = static_cast<T*>(a.halo_out);
+  const size_t hq = (size_t)q * 4;
+  const int L = a.levels;
+  int f, y;
+  if (pass_line<C>(f, y)) {
+    const T* row = tile + field_base<C>(f) + y * C::RS;
+    if constexpr (SCH == S_LBM) {
+      if (pop_enters(0, f)) h[((hq + 0) * 3 + pop_slot(0, f)) * C::S + y] = bl53_inv_edge<C, T, true>(row, L);
+      if (pop_enters(1, f)) h[((hq + 1) * 3 + pop_slot(1, f)) * C::S + y] = bl53_inv_edge<C, T, false>(row, L);
+    } else {
+      h[((hq + 0) * C::NSLOT + f) * C::S + y] = bl53_inv_edge<C, T, true>(row, L);
+      h[((hq + 1) * C::NSLOT + f) * C::S + y] = bl53_inv_edge<C, T, false>(row, L);
+    }
+  } else if ((int)(threadIdx.x >> 6) >= C::NPASS) {
+    // helper item: field g, row HI (even item) or LO (odd item)
+    const int ht = (int)threadIdx.x - 64 * C::NPASS;
+    const int g = ht >> 1;
+    if (g < C::M) {
+      const bool hi = (ht & 1) == 0;
+      const int side = hi ? 2 : 3;
+      const bool need = SCH == S_LBM ? pop_enters(side, g) : true;
+      if (need) {
+        T v[C::S];
+        load_row<C>(v, tile, field_base<C>(g), hi ? C::HI : C::LO);
+        LF::inv(v, L);
+        T* dst = SCH == S_LBM ? h + ((hq + side) * 3 + pop_slot(side, g)) * C::S
+                              : h + ((hq + side) * C::NSLOT + g) * C::S;
+#pragma unroll
+        for (int x = 0; x < C::S; ++x) dst[x] = v[x];
+      }
+    }
+  }
+}
+
+template <class C, class T, int WAV, int SCH>
+__device__ __forceinline__ void export_rows(const PatchArgs& a, int q, T* tile, const T* ghost) {
+  if constexpr (WAV == W_BL53) export_rows_bl53<C, T, SCH>(a, q, tile);
+  else row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, tile, ghost);
+}
+
+// ---------------------------------------------------------------------------
 // Stencils (S4)
 // ---------------------------------------------------------------------------
 
@@ -1306,7 +1382,7 @@ __device__ __forceinline__ void step_one_patch(const PatchArgs& a, int q, SM& sm
   LBMZ_MARK(4);
   if (compact_any<C, T, WAV, true, VF>(a, q, sm)) {
     LBMZ_MARK(5);
-    row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
+    export_rows<C, T, WAV, SCH>(a, q, sm.tile, sm.ghost);
     LBMZ_MARK(6);
   }
 }
@@ -1395,7 +1471,7 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
       ok = compact_any<C, T, WAV, false, VF>(a, q, sm);
     }
     if (!ok) return;
-    row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
+    export_rows<C, T, WAV, SCH>(a, q, sm.tile, sm.ghost);
     return;
   }
   ListRegs<C, T> lr;
@@ -1405,7 +1481,7 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
   if (a.mode == AUX_RESTORE) {
     expand_any<C, T, WAV, true, VF>(a, q, sm, lr);
     totals_finish<C, T, false>(a, a.partials_out + (size_t)q * C::M, a.levels, sm);
-    row_pass<C, T, WAV, SCH, ROW_INV_EXPORT>(a, q, sm.tile, sm.ghost);
+    export_rows<C, T, WAV, SCH>(a, q, sm.tile, sm.ghost);
   } else {
     expand_any<C, T, WAV, false, VF>(a, q, sm, lr);
     row_pass<C, T, WAV, SCH, ROW_INV_DENSE>(a, q, sm.tile, sm.ghost);
