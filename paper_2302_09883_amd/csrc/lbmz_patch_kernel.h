@@ -20,8 +20,10 @@
 //   S7  compaction straight from registers: one ballot per 64-bit mask
 //       word, one bump allocation per patch, coalesced value stores,
 //   S9  FP64 totals from the coarse samples,
-//   S8  column inverse in the same registers, row inverse, and export of
-//       the boundary lines the neighbours need at the next step.
+//   S8  column inverse in the same registers, then (BL5/3) only the values
+//       the neighbours read at the next step: the rows' values at nodes 1
+//       and P - 1 by their lifting dependency chain, and the full inverse of
+//       the two exported rows (Haar: the full row inverse).
 #pragma once
 
 #include <hip/hip_runtime.h>
