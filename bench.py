@@ -240,6 +240,30 @@ def cpu_baseline(steps: int = 4):
                       f"cells) at eps={PRIMARY_EPS}, float32 NumPy oracle on one core, {dt:.1f} s"}
 
 
+def hbm_point(n: int, steps: int, warmup: int = 5):
+    """The operating point bound by HBM bytes: eps = 0 keeps every coefficient
+    (bitmask records, stored density ~1).  Plain launches, no error run."""
+    from paper_2302_09883_amd import Context
+    from synth import shear_layer_macroscopic
+
+    macro = [a.astype(np.float32) for a in shear_layer_macroscopic(n, seed=SEED)]
+    ctx = Context(n, scheme="d2q9_bgk", dtype="f32", p=P, wavelet="bl53", levels=LEVELS, eps=0.0, tau=TAU)
+    ctx.set_macroscopic(*macro)
+    ctx.step(warmup)
+    s0 = ctx.stats()
+    ctx.step(steps)
+    s1 = ctx.stats()
+    k_ms = s1["ms_last_call"] / steps
+    npatch = (n // P) ** 2
+    b = 2.0 * 0.5 * (s0["store_bytes"] + s1["store_bytes"]) + 2.0 * halo_bytes(npatch)
+    gbs = b / (k_ms * 1e-3) / 1e9
+    ctx.close()
+    return {"grid": n, "eps": 0.0, "steps": steps, "kernel_ms_avg": _sig(k_ms), "mlups": _sig(n * n / (k_ms * 1e-3) / 1e6),
+            "rho_nz": _sig(s1["nnz_total"] / (npatch * 9 * (P + 1) ** 2)), "bytes_per_launch": round(b),
+            "hbm_gbs": _sig(gbs), "hbm_frac": _sig(gbs / HBM_PEAK_GBS),
+            "alu_frac": _sig(flops_per_patch() * npatch / (k_ms * 1e-3) / 1e12 / VALU_PEAK_TFLOPS)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +275,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="time one workgroup per patch with plain launches instead of the autotuned mode")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-hbm-points", action="store_true",
+                    help="skip the eps=0 runs at 2048^2 and 4096^2 (the HBM-bound operating points)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (the reference kernel for counter scaling)")
     args = ap.parse_args()
@@ -305,6 +331,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    hbm_points = None
+    if not args.no_hbm_points:
+        hbm_points = [hbm_point(N, 200), hbm_point(2 * N, 100)]
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_steps)
@@ -332,6 +362,7 @@ def main():
         "sweep": [{k: _sig(v) for k, v in p.items()} for p in points],
         "uncompressed_mlups": round(ref_mlups, 1),
         "roofline": roof,
+        "hbm_bound_points": hbm_points,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
