@@ -490,27 +490,39 @@ __device__ void stream_field(const PatchArgs& a, int q, int f, float* scr, SM& s
     }
   const int shift = cf[0] + C::S * cf[1] + C::S2 * cf[2];
   float* dst = scr + (size_t)f * C::SF;
-  constexpr int U = 4;   // nodes per thread and iteration (independent LDS reads in flight)
-  for (int t0 = threadIdx.x; t0 < C::S3; t0 += U * C::NT) {
-    float val[U];
-    bool in[U];
+  // Each thread keeps one x and steps through the x-rows (y, z) RPP at a time
+  // (RPP * S of the threads take part), so that y and z advance by additions.
+  constexpr int RPP = C::NT / C::S;
+  constexpr int U = 4;   // rows per thread and iteration (independent LDS reads in flight)
+  if (threadIdx.x < RPP * C::S) {
+    const int x = threadIdx.x % C::S;
+    const int r0 = threadIdx.x / C::S;
+    const bool inx = (unsigned)(x - cf[0]) < (unsigned)C::S;
+    int y = r0 % C::S, z = r0 / C::S;   // row r = y + S z, starting at r0
+    for (int r = r0; r < C::S2; r += U * RPP) {
+      float val[U];
+      bool in[U];
+      int t[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * C::NT;
-      const int z = t / C::S2;
-      const int r = t - z * C::S2;
-      const int y = r / C::S;
-      const int x = r - y * C::S;
-      const int mx = x - cf[0], my = y - cf[1], mz = z - cf[2];
-      in[u] = t < C::S3 && (unsigned)mx < (unsigned)C::S && (unsigned)my < (unsigned)C::S &&
-              (unsigned)mz < (unsigned)C::S;
-      // clamped address: the read is unconditional, the store is not
-      const int src = t - shift;
-      val[u] = sm.tile[src < 0 ? 0 : (src >= C::S3 ? C::S3 - 1 : src)];
+      for (int u = 0; u < U; ++u) {
+        t[u] = x + C::S * (y + C::S * z);
+        in[u] = r + u * RPP < C::S2 && inx && (unsigned)(y - cf[1]) < (unsigned)C::S &&
+                (unsigned)(z - cf[2]) < (unsigned)C::S;
+        // clamped address: the read is unconditional, the store is not
+        const int src = t[u] - shift;
+        val[u] = sm.tile[src < 0 ? 0 : (src >= C::S3 ? C::S3 - 1 : src)];
+        // advance by RPP rows: RPP / S planes and RPP % S rows, at most one more wrap
+        y += RPP % C::S;
+        z += RPP / C::S;
+        if (y >= C::S) {
+          y -= C::S;
+          ++z;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (in[u]) dst[t[u]] = val[u];
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (in[u]) dst[t0 + u * C::NT] = val[u];
   }
   const int npx = a.npx;
   const int pz = q / (npx * npx), py = (q / npx) % npx, px = q % npx;
