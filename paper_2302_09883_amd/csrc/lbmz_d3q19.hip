@@ -261,7 +261,11 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
   const int L = a.levels;
   const float eps = (float)a.eps;
   P3_START();
-  // counts: one ballot per 64-node chunk
+  // counts: one ballot per 64-node chunk; wave w owns the chunks
+  // c = w + NW k and keeps bit k of `nonempty` for those with a kept
+  // coefficient (a wave-uniform mask, held across the barriers)
+  static_assert((C::W + C::NW - 1) / C::NW <= 64, "one bit per owned chunk");
+  unsigned long long nonempty = 0ull;
   constexpr int U = 4;   // chunks per wave and iteration (independent LDS reads in flight)
   for (int c0 = wave; c0 < C::W; c0 += U * C::NW) {
     float v[U];
@@ -298,6 +302,7 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
         }
       }
       const unsigned long long bits = __ballot(v[u] != 0.f);
+      if (bits != 0ull) nonempty |= 1ull << ((c - wave) / C::NW);
       if (lane == 0 && c < C::W) sm.pre[c] = (uint32_t)__popcll(bits);
     }
   }
@@ -330,29 +335,44 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
   float* vals = reinterpret_cast<float*>(rec);
   uint16_t* idx = reinterpret_cast<uint16_t*>(rec + vb);
   unsigned long long* words = reinterpret_cast<unsigned long long*>(rec + vb);
-  for (int c0 = wave; c0 < C::W; c0 += U * C::NW) {
-    float v[U];
-    uint32_t pre[U];
+  if (ismask) {
+    // bitmask record: every chunk's word is written, empty or not
+    for (int c0 = wave; c0 < C::W; c0 += U * C::NW) {
+      float v[U];
+      uint32_t pre[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = c0 + u * C::NW;
-      const int t = 64 * c + lane;
-      const float r = sm.tile[t < C::S3 ? t : C::S3 - 1];
-      const uint32_t p = sm.pre[c < C::W ? c : C::W - 1];
-      v[u] = t < C::S3 ? r : 0.f;
-      pre[u] = c < C::W ? p : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = c0 + u * C::NW;
-      const int t = 64 * c + lane;
-      const unsigned long long bits = __ballot(v[u] != 0.f);
-      const uint32_t k = pre[u] + mbcnt64(bits);
-      if (v[u] != 0.f) {
-        vals[k] = v[u];
-        if (!ismask) idx[k] = (uint16_t)t;
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * C::NW;
+        const int t = 64 * c + lane;
+        const float r = sm.tile[t < C::S3 ? t : C::S3 - 1];
+        const uint32_t p = sm.pre[c < C::W ? c : C::W - 1];
+        v[u] = t < C::S3 ? r : 0.f;
+        pre[u] = c < C::W ? p : 0u;
       }
-      if (ismask && lane == 0 && c < C::W) words[c] = bits;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * C::NW;
+        const unsigned long long bits = __ballot(v[u] != 0.f);
+        if (v[u] != 0.f) vals[pre[u] + mbcnt64(bits)] = v[u];
+        if (lane == 0 && c < C::W) words[c] = bits;
+      }
+    }
+  } else {
+    // index list: only the wave's chunks with a kept coefficient
+    {
+      unsigned long long m = nonempty;
+      while (m != 0ull) {
+        const int c = wave + C::NW * __builtin_ctzll(m);
+        m &= m - 1ull;
+        const int t = 64 * c + lane;
+        const float v = t < C::S3 ? sm.tile[t] : 0.f;
+        const unsigned long long bits = __ballot(v != 0.f);
+        if (v != 0.f) {
+          const uint32_t k = sm.pre[c] + mbcnt64(bits);
+          vals[k] = v;
+          idx[k] = (uint16_t)t;
+        }
+      }
     }
   }
   // zero padding: after the values, and from the end of the indices or
