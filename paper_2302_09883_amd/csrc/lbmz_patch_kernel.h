@@ -1165,16 +1165,20 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm
   totals_partial<C, T>(part, sm);
   LBMZ_MARK(8);
 
-  // Counts: one ballot per owned row (and the shared row), restricted to the
-  // lanes that hold a line by a scalar mask.  The shared-column wave parks
-  // its thresholded coefficients in the ghost buffer (unused from here on),
-  // where wave 0 counts them and the field waves store them.
+  // Counts: the owned rows by per-lane counts summed over the wave (vector
+  // compares only: a ballot per row costs more scalar work than it saves),
+  // the shared row by one ballot restricted to the lanes that hold a line.
+  // The shared-column wave parks its thresholded coefficients in the ghost
+  // buffer (unused from here on), where wave 0 counts them and the field
+  // waves store them.
   T* rimc = sm.ghost;   // [field][y]
   const unsigned long long actm = __ballot(act);
   if (wave < C::M) {
-    int run = 0;
+    // lanes without a line hold zeros
+    int cnt = 0;
 #pragma unroll
-    for (int y = 0; y < C::P; ++y) run += __popcll(__ballot(v[y] != T(0)) & actm);
+    for (int y = 0; y < C::P; ++y) cnt += (v[y] != T(0)) ? 1 : 0;
+    const int run = __shfl(wave_incl_scan(cnt), 63, 64);
     unsigned long long rowb = 0ull;
     if constexpr (C::RIM) rowb = __ballot(v[C::P] != T(0)) & actm;
     if (lane == 0) {

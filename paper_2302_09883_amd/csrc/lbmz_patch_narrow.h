@@ -200,14 +200,13 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
       for (int c = 0; c <= C::LMAX; ++c)
         if (c <= L) sm.nq.smax[f][c * L1 + cx] = mc[c];
     }
-    // kept details per row (sample positions excluded)
-    int run = 0;
+    // kept details (sample positions excluded): per-lane counts summed over
+    // the wave; lanes without a line hold zeros
+    const bool samp_lane = act && cx == 0;
+    int cnt = 0;
 #pragma unroll
-    for (int y = 0; y < C::P; ++y) {
-      unsigned long long b = __ballot(v[y] != T(0)) & actm;
-      if ((y & lmask) == 0) b &= ~samp_lanes;
-      run += __popcll(b);
-    }
+    for (int y = 0; y < C::P; ++y) cnt += (v[y] != T(0) && !((y & lmask) == 0 && samp_lane)) ? 1 : 0;
+    const int run = __shfl(wave_incl_scan(cnt), 63, 64);
     unsigned long long rowb = 0ull;
     if constexpr (C::RIM) rowb = __ballot(v[C::P] != T(0)) & actm & ~samp_lanes;
     if (lane == 0) {
