@@ -511,28 +511,37 @@ __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >=
 // D2Q9: W/E strips (rows 0..S-1) for the x shift of the row pass, and the
 // S/N ghost rows of the tile, already shifted in x: row -1 of population i
 // holds f_i(x - c_ix, -1), row S holds f_i(x - c_ix, S).
+// Ghost value k (0 <= k < 4 * 3 * S): loaded into v; returns its LDS slot.
 template <class C, class T>
-__device__ __forceinline__ void gather_lbm(const PatchArgs& a, int q, T* tile, T* ghost) {
+__device__ __forceinline__ T* gather_lbm_at(const PatchArgs& a, int q, int k, T* tile, T* ghost, T& v) {
   const T* h = static_cast<const T*>(a.halo_in);
   const int px = q % a.npx;
   const int py = q / a.npx;
+  const int side = k / (3 * C::S);
+  const int rem = k - side * (3 * C::S);
+  const int slot = rem / C::S;
+  const int j = rem - slot * C::S;
+  if (side < 2) {
+    const int nb = wrap(px + (side == 0 ? -1 : 1), a.npx) + a.npx * py;
+    v = h[((size_t)(nb * 4 + side) * 3 + slot) * C::S + j];
+    return ghost + k;
+  }
+  const int pop = D2Q9::SIDE_POP[side][slot];
+  const int xs = j - D2Q9::CX[pop];
+  const int ox = xs < 0 ? -1 : (xs >= C::S ? 1 : 0);
+  const int xl = xs - C::P * ox;
+  const int nb = wrap(px + ox, a.npx) + a.npx * wrap(py + (side == 2 ? -1 : 1), a.npx);
+  const int row = side == 2 ? -1 : C::S;
+  v = h[((size_t)(nb * 4 + side) * 3 + slot) * C::S + xl];
+  return tile + field_base<C>(pop) + row * C::RS + j;
+}
+
+template <class C, class T>
+__device__ __forceinline__ void gather_lbm(const PatchArgs& a, int q, T* tile, T* ghost) {
   for (int k = threadIdx.x; k < 4 * 3 * C::S; k += C::NT) {
-    const int side = k / (3 * C::S);
-    const int rem = k - side * (3 * C::S);
-    const int slot = rem / C::S;
-    const int j = rem - slot * C::S;
-    if (side < 2) {
-      const int nb = wrap(px + (side == 0 ? -1 : 1), a.npx) + a.npx * py;
-      ghost[k] = h[((size_t)(nb * 4 + side) * 3 + slot) * C::S + j];
-    } else {
-      const int pop = D2Q9::SIDE_POP[side][slot];
-      const int xs = j - D2Q9::CX[pop];
-      const int ox = xs < 0 ? -1 : (xs >= C::S ? 1 : 0);
-      const int xl = xs - C::P * ox;
-      const int nb = wrap(px + ox, a.npx) + a.npx * wrap(py + (side == 2 ? -1 : 1), a.npx);
-      const int row = side == 2 ? -1 : C::S;
-      tile[field_base<C>(pop) + row * C::RS + j] = h[((size_t)(nb * 4 + side) * 3 + slot) * C::S + xl];
-    }
+    T v;
+    T* d = gather_lbm_at<C, T>(a, q, k, tile, ghost, v);
+    *d = v;
   }
 }
 
@@ -981,7 +990,7 @@ __device__ __forceinline__ void prefetch_lists(const PatchArgs& a, int q, ListRe
   }
 }
 
-template <class C, class T, int WAV, bool TOT, class SM>
+template <class C, class T, int WAV, bool TOT, bool PREZ, class SM>
 __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm, const ListRegs<C, T>& lr) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
   const int tid = threadIdx.x;
@@ -996,10 +1005,12 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
 
   // Index-list records: the helper waves (no line in the passes) hold their
   // entries (prefetch_lists) and zero their tiles, so that the line waves
-  // carry no list state.
+  // carry no list state.  With PREZ the tiles are already zero: the D2Q9
+  // step zeroes every field's owned rows at the start of the patch, under
+  // the latency of its ghost loads.
   const bool helper = wave >= C::NPASS;
   const int ht = tid - 64 * C::NPASS;
-  if (helper) {
+  if (!PREZ && helper) {
 #pragma unroll
     for (int f = 0; f < C::M; ++f)
       if (!(te(2 * f + 1) & MASK_BIT)) zero_span<T>(sm.tile + C::Lay::fb(f), C::S * C::RS, ht, C::NHT);
@@ -1346,9 +1357,9 @@ namespace lbmz {
 // Kernels
 // ---------------------------------------------------------------------------
 
-template <class C, class T, int WAV, bool TOT, int VF, class SM>
+template <class C, class T, int WAV, bool TOT, int VF, bool PREZ = false, class SM>
 __device__ __forceinline__ void expand_any(const PatchArgs& a, int q, SM& sm, const ListRegs<C, T>& lr) {
-  if constexpr (VF == VF_F32) expand_columns<C, T, WAV, TOT>(a, q, sm, lr);
+  if constexpr (VF == VF_F32) expand_columns<C, T, WAV, TOT, PREZ>(a, q, sm, lr);
   else expand_columns_q<C, T, WAV, TOT, VF>(a, q, sm);
 }
 
@@ -1360,13 +1371,33 @@ __device__ __forceinline__ bool compact_any(const PatchArgs& a, int q, SM& sm) {
 
 // The loads that start a patch, issued before the barrier that precedes the
 // expansion: the index-list entries (float32 records), the ghost values (S3)
-// and the offset-table entries.
+// and the offset-table entries; for D2Q9 with float32 records, also the
+// zeroing of the fields' owned rows, between the loads and their LDS stores.
 template <class C, class T, int SCH, int VF, class SM>
 __device__ __forceinline__ void begin_patch(const PatchArgs& a, int q, SM& sm, ListRegs<C, T>& lr) {
   if constexpr (VF == VF_F32) prefetch_lists<C, T>(a, q, lr);
-  prefetch_table<C>(a, q, sm);
-  if constexpr (SCH == S_LBM) gather_lbm<C, T>(a, q, sm.tile, sm.ghost);
-  else gather_fv<C, T>(a, q, sm.ghost);
+  if constexpr (SCH == S_LBM && VF == VF_F32) {
+    // The ghost value and the table entry of each thread are loaded into
+    // registers; while they are in flight every thread zeroes its share of
+    // the fields' owned rows (index-list records scatter into zeroed tiles;
+    // the ghost rows outside them are not touched); then the loaded values
+    // go to LDS.
+    static_assert(4 * 3 * C::S <= C::NT, "one ghost value per thread");
+    const int tid = threadIdx.x;
+    T gv = T(0);
+    T* gd = nullptr;
+    if (tid < 4 * 3 * C::S) gd = gather_lbm_at<C, T>(a, q, tid, sm.tile, sm.ghost, gv);
+    uint32_t tv = 0u;
+    if (tid < 2 * C::M) tv = a.table_in[2 * (size_t)q * C::M + tid];
+#pragma unroll
+    for (int f = 0; f < C::M; ++f) zero_span<T>(sm.tile + C::Lay::fb(f), C::S * C::RS, tid, C::NT);
+    if (gd != nullptr) *gd = gv;
+    if (tid < 2 * C::M) sm.te[tid] = tv;
+  } else {
+    prefetch_table<C>(a, q, sm);
+    if constexpr (SCH == S_LBM) gather_lbm<C, T>(a, q, sm.tile, sm.ghost);
+    else gather_fv<C, T>(a, q, sm.ghost);
+  }
 }
 
 // One step (time n -> n + 1) of patch q, S1..S9, after begin_patch and a barrier.
@@ -1374,7 +1405,7 @@ template <class C, class T, int WAV, int SCH, int VF, class SM>
 __device__ __forceinline__ void step_one_patch(const PatchArgs& a, int q, SM& sm, const ListRegs<C, T>& lr) {
   LBMZ_MARK(0);
   LBMZ_MARK(14);
-  expand_any<C, T, WAV, false, VF>(a, q, sm, lr);
+  expand_any<C, T, WAV, false, VF, SCH == S_LBM && VF == VF_F32>(a, q, sm, lr);
   LBMZ_MARK(1);
   row_pass<C, T, WAV, SCH, SCH == S_LBM ? ROW_INV_SHIFT : ROW_INV>(a, q, sm.tile, sm.ghost);
   __syncthreads();
