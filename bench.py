@@ -83,11 +83,18 @@ TRAFFIC_FILE = "profiles/traffic_patch_step_d2q9_2048_eps1e-4.txt"
 
 
 def kernel_source_digest() -> str:
+    """First 16 hex digits of the SHA-256 of the kernel sources' code: line
+    comments, trailing blanks and empty lines are dropped, so that a change of
+    comments alone does not mark measured counters as stale."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+            for line in fh:
+                code = re.sub(r"//.*$", "", line).rstrip()
+                if code:
+                    h.update(code.encode("utf-8") + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -8,7 +8,8 @@
 // column-per-lane accesses are both bank-conflict free.
 //
 // One step of one patch:
-//   S3  ghost values of the neighbours' previous export are loaded first;
+//   S3  ghost values of the neighbours' previous export are loaded first
+//       (D2Q9: the tiles are zeroed while those loads are in flight);
 //   S1  the patch's records are expanded straight into the column registers
 //       (bitmask records) or scattered through LDS (index-list records),
 //   S2  inverse transform: columns (y) then rows (x), coarse to fine; for
@@ -17,8 +18,9 @@
 //       FV: upwind flux sum) of every tile node;
 //   S5  forward transform: rows (x), then in one column pass: columns (y),
 //   S6  hard threshold (Section 2.2),
-//   S7  compaction straight from registers: one ballot per 64-bit mask
-//       word, one bump allocation per patch, coalesced value stores,
+//   S7  compaction straight from registers: per-lane counts, one ballot
+//       per 64-bit mask word, one bump allocation per patch, coalesced
+//       value stores,
 //   S9  FP64 totals from the coarse samples,
 //   S8  column inverse in the same registers, then (BL5/3) only the values
 //       the neighbours read at the next step: the rows' values at nodes 1
