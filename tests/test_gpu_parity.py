@@ -157,6 +157,39 @@ def test_one_step_from_common_state(geom, eps):
     assert np.max(np.abs(ctx.fields() - lossy)) <= 16 * u * scale
 
 
+@pytest.mark.parametrize("geom", [g for g in GEOMS if g[1] == "d2q9_bgk"])
+def test_one_step_mixed_record_encodings(geom):
+    # every patch's store holds both encodings: rough populations (bitmask
+    # records, expanded into registers) beside smooth ones (index lists,
+    # scattered into tiles zeroed at the start of the patch)
+    n, scheme, dtype, p, wavelet, levels = geom
+    eps = 1e-3
+    _say("one-step mixed encodings", geom, eps)
+    ctx = make_ctx(n, scheme, dtype, p, wavelet, levels, eps)
+    twin = oracle_twin(ctx)
+    state = _initial_state(n, scheme, ctx.np_dtype, seed=5)
+    rng = np.random.default_rng(7)
+    state[:4] += (0.02 * rng.standard_normal(state[:4].shape)).astype(state.dtype)
+    twin.set_grid(state)
+    table, pool = O.encode_store(twin.coef)
+    ismask = (table[..., 1] & O.MASK_BIT) != 0
+    assert ismask.any(axis=1).all() and (~ismask).any(axis=1).all()
+    ctx.put_store(table, pool)
+    ctx.step(1)
+    twin.step(1)
+    got, _, _ = gpu_coefficients(ctx)
+    want = twin.coef
+    u = np.finfo(ctx.np_dtype).eps
+    scale = float(np.max(np.abs(twin.grid())))
+    delta = 256 * u * scale
+    thr = np.broadcast_to(twin.thr, want.shape)
+    kg, kw = got != 0, want != 0
+    flip = kg != kw
+    assert np.all(borderline(np.where(kg, got, want), thr, delta)[flip]), int(flip.sum())
+    both = kg & kw
+    assert np.max(np.abs(got[both] - want[both]), initial=0.0) <= delta
+
+
 def test_cfg1_full_run_against_oracle():
     # transport workload: 256^2, 32^2 patches, Haar, float64, L = 4, eps = 1e-4, 100 steps
     _say("cfg1 full")
