@@ -262,10 +262,12 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
   const float eps = (float)a.eps;
   P3_START();
   // counts: one ballot per 64-node chunk; wave w owns the chunks
-  // c = w + NW k and keeps bit k of `nonempty` for those with a kept
-  // coefficient (a wave-uniform mask, held across the barriers)
+  // c = w + NW k, keeps bit k of `nonempty` for those with a kept
+  // coefficient (a wave-uniform mask, held across the barriers) and the
+  // count of chunk k in lane k, stored once per wave after the loop
   static_assert((C::W + C::NW - 1) / C::NW <= 64, "one bit per owned chunk");
   unsigned long long nonempty = 0ull;
+  int mycnt = 0;   // lane k: kept count of the wave's chunk wave + NW k
   constexpr int U = 4;   // chunks per wave and iteration (independent LDS reads in flight)
   for (int c0 = wave; c0 < C::W; c0 += U * C::NW) {
     float v[U];
@@ -302,9 +304,14 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
         }
       }
       const unsigned long long bits = __ballot(v[u] != 0.f);
-      if (bits != 0ull) nonempty |= 1ull << ((c - wave) / C::NW);
-      if (lane == 0 && c < C::W) sm.pre[c] = (uint32_t)__popcll(bits);
+      const int k = (c - wave) / C::NW;
+      if (bits != 0ull) nonempty |= 1ull << k;
+      mycnt = (lane == k) ? __popcll(bits) : mycnt;
     }
+  }
+  {
+    const int c = wave + C::NW * lane;
+    if (c < C::W) sm.pre[c] = (uint32_t)mycnt;
   }
   __syncthreads();
   P3_MARK(10);
