@@ -241,9 +241,18 @@ __device__ void expand_field(const PatchArgs& a, int q, int f, SM& sm) {
     }
   } else {
     const uint16_t* idx = reinterpret_cast<const uint16_t*>(rec + vb);
+    // the first NT entries are loaded before the zeroing, under which their
+    // latency passes; they are scattered after the barrier
+    int k0 = -1;
+    float v0 = 0.f;
+    if (tid < (int)nnz) {
+      k0 = idx[tid];
+      v0 = vals[tid];
+    }
     zero_span<float>(sm.tile, C::S3, tid, C::NT);
     __syncthreads();
-    for (int k = tid; k < (int)nnz; k += C::NT) sm.tile[idx[k]] = vals[k];
+    if (k0 >= 0) sm.tile[k0] = v0;
+    for (int k = tid + C::NT; k < (int)nnz; k += C::NT) sm.tile[idx[k]] = vals[k];
   }
   __syncthreads();
 }
