@@ -511,6 +511,56 @@ __device__ __forceinline__ int neighbour(int px, int py, int pz, int ox, int oy,
 // lies in the tile copy it from LDS; the others (the planes n_a = 0 or S - 1
 // of the axes along which c_f points) read it from the neighbours' halo,
 // one independent load per node.
+// Ghost node i (< S^2) of population f on the receiving plane of axis ax
+// (c_f[ax] != 0): its value from the neighbour's halo into val; returns its
+// index in the patch, or -1 when the node is taken by the plane of another
+// axis (an edge line).
+template <class C>
+__device__ __forceinline__ int ghost_at(const float* halo, int px, int py, int pz, int npx, const int* cf,
+                                        const int* sl, int ax, int i, float& val) {
+  // receiving plane n_ax = 0 (c > 0) or S - 1 (c < 0); (u, v) over the
+  // other two axes b1 < b2
+  const int b1 = ax == 0 ? 1 : 0;
+  const int b2 = ax == 2 ? 1 : 2;
+  const int c1 = b1 == 0 ? cf[0] : cf[1];
+  const int c2 = b2 == 1 ? cf[1] : cf[2];
+  const int na = cf[ax] > 0 ? 0 : C::S - 1;
+  const int o = cf[ax] > 0 ? -1 : 1;   // neighbour offset along ax
+  const int s_ax = ax == 0 ? 1 : (ax == 1 ? C::S : C::S2);
+  const int s_1 = b1 == 0 ? 1 : C::S;
+  const int s_2 = b2 == 1 ? C::S : C::S2;
+  const int v = i / C::S;
+  const int u = i - v * C::S;
+  const int m1 = u - c1, m2 = v - c2;
+  const int o1 = m1 < 0 ? -1 : (m1 >= C::S ? 1 : 0);
+  const int o2 = m2 < 0 ? -1 : (m2 >= C::S ? 1 : 0);
+  if (o1 == 0 && o2 == 0) {
+    // a face of the neighbour along ax
+    const int qn = neighbour(px, py, pz, ax == 0 ? o : 0, ax == 1 ? o : 0, ax == 2 ? o : 0, npx);
+    val = halo[(size_t)qn * C::HALO + (size_t)(2 * ax + (cf[ax] > 0 ? 1 : 0)) * C::FACE +
+               (size_t)(ax == 0 ? sl[0] : (ax == 1 ? sl[1] : sl[2])) * C::S2 + m1 + C::S * m2];
+  } else {
+    // off the tile along ax and one more axis b: an edge line, taken by
+    // the plane of the smaller of the two axes
+    const int b = o1 != 0 ? b1 : b2;
+    if (b < ax) return -1;
+    const int ob = o1 != 0 ? o1 : o2;
+    const int oxx = (ax == 0 ? o : 0) + (b == 0 ? ob : 0);
+    const int oyy = (ax == 1 ? o : 0) + (b == 1 ? ob : 0);
+    const int ozz = (ax == 2 ? o : 0) + (b == 2 ? ob : 0);
+    const int qn = neighbour(px, py, pz, oxx, oyy, ozz, npx);
+    // pair (x,y), (x,z) or (y,z) and the coordinate along the third axis
+    const int lo = ax < b ? ax : b, hi = ax < b ? b : ax;
+    const int pr = (lo == 0 && hi == 1) ? 0 : (lo == 0 ? 1 : 2);
+    const int ca = lo == 0 ? cf[0] : cf[1];
+    const int cb = hi == 1 ? cf[1] : cf[2];
+    const int w = o1 != 0 ? m2 : m1;   // the in-range coordinate
+    const int e = 4 * pr + (ca > 0 ? 1 : 0) + 2 * (cb > 0 ? 1 : 0);
+    val = halo[(size_t)qn * C::HALO + 6 * (size_t)C::FACE + (size_t)e * C::S + w];
+  }
+  return na * s_ax + u * s_1 + v * s_2;
+}
+
 template <class C, class SM>
 __device__ void stream_field(const PatchArgs& a, int q, int f, float* scr, SM& sm) {
   int cf[3] = {0, 0, 0}, sl[3] = {0, 0, 0};
@@ -526,6 +576,24 @@ __device__ void stream_field(const PatchArgs& a, int q, int f, float* scr, SM& s
     }
   const int shift = cf[0] + C::S * cf[1] + C::S2 * cf[2];
   float* dst = scr + (size_t)f * C::SF;
+  // the ghost values are loaded before the in-tile pass, under which their
+  // latency passes, and stored after it (the two passes write disjoint nodes)
+  const int npx = a.npx;
+  const int pz = q / (npx * npx), py = (q / npx) % npx, px = q % npx;
+  const float* halo = static_cast<const float*>(a.halo_in);
+  constexpr int GI = (C::S2 + C::NT - 1) / C::NT;
+  float gv[3][GI];
+  int gd[3][GI];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+    for (int j = 0; j < GI; ++j) {
+      const int i = threadIdx.x + j * C::NT;
+      gv[ax][j] = 0.f;
+      gd[ax][j] = -1;
+      if (cf[ax] != 0 && i < C::S2) gd[ax][j] = ghost_at<C>(halo, px, py, pz, npx, cf, sl, ax, i, gv[ax][j]);
+    }
+  }
   // Each thread keeps one x and steps through the x-rows (y, z) RPP at a time
   // (RPP * S of the threads take part), so that y and z advance by additions.
   constexpr int RPP = C::NT / C::S;
@@ -560,56 +628,11 @@ __device__ void stream_field(const PatchArgs& a, int q, int f, float* scr, SM& s
         if (in[u]) dst[t[u]] = val[u];
     }
   }
-  const int npx = a.npx;
-  const int pz = q / (npx * npx), py = (q / npx) % npx, px = q % npx;
-  const float* halo = static_cast<const float*>(a.halo_in);
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
-    if (cf[ax] == 0) continue;
-    // receiving plane n_ax = 0 (c > 0) or S - 1 (c < 0); (u, v) over the
-    // other two axes b1 < b2
-    const int b1 = ax == 0 ? 1 : 0;
-    const int b2 = ax == 2 ? 1 : 2;
-    const int c1 = b1 == 0 ? cf[0] : cf[1];
-    const int c2 = b2 == 1 ? cf[1] : cf[2];
-    const int na = cf[ax] > 0 ? 0 : C::S - 1;
-    const int o = cf[ax] > 0 ? -1 : 1;   // neighbour offset along ax
-    const int s_ax = ax == 0 ? 1 : (ax == 1 ? C::S : C::S2);
-    const int s_1 = b1 == 0 ? 1 : C::S;
-    const int s_2 = b2 == 1 ? C::S : C::S2;
-    for (int i = threadIdx.x; i < C::S2; i += C::NT) {
-      const int v = i / C::S;
-      const int u = i - v * C::S;
-      const int m1 = u - c1, m2 = v - c2;
-      const int o1 = m1 < 0 ? -1 : (m1 >= C::S ? 1 : 0);
-      const int o2 = m2 < 0 ? -1 : (m2 >= C::S ? 1 : 0);
-      float val;
-      if (o1 == 0 && o2 == 0) {
-        // a face of the neighbour along ax
-        const int qn = neighbour(px, py, pz, ax == 0 ? o : 0, ax == 1 ? o : 0, ax == 2 ? o : 0, npx);
-        val = halo[(size_t)qn * C::HALO + (size_t)(2 * ax + (cf[ax] > 0 ? 1 : 0)) * C::FACE +
-                   (size_t)(ax == 0 ? sl[0] : (ax == 1 ? sl[1] : sl[2])) * C::S2 + m1 + C::S * m2];
-      } else {
-        // off the tile along ax and one more axis b: an edge line, taken by
-        // the plane of the smaller of the two axes
-        const int b = o1 != 0 ? b1 : b2;
-        if (b < ax) continue;
-        const int ob = o1 != 0 ? o1 : o2;
-        const int oxx = (ax == 0 ? o : 0) + (b == 0 ? ob : 0);
-        const int oyy = (ax == 1 ? o : 0) + (b == 1 ? ob : 0);
-        const int ozz = (ax == 2 ? o : 0) + (b == 2 ? ob : 0);
-        const int qn = neighbour(px, py, pz, oxx, oyy, ozz, npx);
-        // pair (x,y), (x,z) or (y,z) and the coordinate along the third axis
-        const int lo = ax < b ? ax : b, hi = ax < b ? b : ax;
-        const int pr = (lo == 0 && hi == 1) ? 0 : (lo == 0 ? 1 : 2);
-        const int ca = lo == 0 ? cf[0] : cf[1];
-        const int cb = hi == 1 ? cf[1] : cf[2];
-        const int w = o1 != 0 ? m2 : m1;   // the in-range coordinate
-        const int e = 4 * pr + (ca > 0 ? 1 : 0) + 2 * (cb > 0 ? 1 : 0);
-        val = halo[(size_t)qn * C::HALO + 6 * (size_t)C::FACE + (size_t)e * C::S + w];
-      }
-      dst[na * s_ax + u * s_1 + v * s_2] = val;
-    }
+#pragma unroll
+    for (int j = 0; j < GI; ++j)
+      if (gd[ax][j] >= 0) dst[gd[ax][j]] = gv[ax][j];
   }
 }
 
