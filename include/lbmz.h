@@ -184,9 +184,14 @@ int lbmz_set_stream(lbmz_ctx* ctx, void* hip_stream);
  * one quarter of the worst-case store. */
 int lbmz_set_pool_capacity(lbmz_ctx* ctx, int64_t bytes);
 
-/* Set field `field` (0 <= field < nfields) of the state from a dense array of
- * `bytes` = n[0] * n[1] * sizeof(dtype) bytes.  Other fields keep their
- * values.  The state is compressed before the next step. */
+/* Set field `field` (0 <= field < nfields) of the state W^0 (Section 1: the
+ * initial condition of the time loop) from a dense array of `bytes` =
+ * n[0] * n[1] * sizeof(dtype) bytes, host or device (src_on_device).  Other
+ * fields keep their values.  The state is compressed -- forward transform of
+ * Section 2.1, hard threshold of Section 2.2, records of Section 2.3.1 -- before
+ * the next step, exactly as the compression stage of Section 3.1.3 does after
+ * every step.  Errors: LBMZ_EINVAL (field out of range, bytes != field size),
+ * LBMZ_EDEVICE, LBMZ_ENOMEM (pool growth). */
 int lbmz_set_field(lbmz_ctx* ctx, int field, const void* src, size_t bytes, int src_on_device);
 
 /* LBM only: set all populations to the equilibrium of the given density and
@@ -194,16 +199,34 @@ int lbmz_set_field(lbmz_ctx* ctx, int field, const void* src, size_t bytes, int 
 int lbmz_set_macroscopic(lbmz_ctx* ctx, const void* rho, const void* ux, const void* uy,
                          size_t bytes_each, int on_device);
 
-/* Advance n >= 0 steps.  One device-to-host read of the control block per
- * call.  A pool overflow is absorbed by regrowing and replaying the
+/* Advance n >= 0 steps of the time loop of Section 1 (W^{n+1} from W^n by the
+ * scheme, two buffers swapped after every step), each step being the
+ * decompress -> step -> compress cycle of Section 3.1.3 carried out patch by
+ * patch: inverse transform of the patch's records, ghost ring from the
+ * neighbours' lossy values (Section 3.1.1, Fig. 3), stencil update, forward
+ * transform, hard threshold (Section 2.2) and compaction (Section 2.3.1).
+ * One device-to-host read of the control block per call; n = 0 returns
+ * LBMZ_OK at once.  A pool overflow is absorbed by regrowing and replaying the
  * remaining steps from the last good state; LBMZ_ENAN leaves the state at
- * the last step whose coefficients were all finite. */
+ * the last step whose coefficients were all finite.  LBMZ_EOVERFLOW only when
+ * the regrowth itself fails. */
 int lbmz_step(lbmz_ctx* ctx, int n);
 
 /* Decompress field `field` of the current state into a dense array of
- * n[0] * n[1] elements (the owned nodes of every patch). */
+ * n[0] * n[1] (n^3 in 3-D) elements of the dtype, host or device
+ * (dst_on_device): the decompression of Section 3.1.3 (records expanded, the
+ * inverse transform of Section 2.1.2 applied), keeping the owned nodes of
+ * every patch (a shared bordering node is written once, by the patch that
+ * owns it; Section 3.1.1).  The state is not changed.  Errors: LBMZ_EINVAL
+ * (field out of range, bytes != field size), LBMZ_EDEVICE. */
 int lbmz_decompress_field(lbmz_ctx* ctx, int field, void* dst, size_t bytes, int dst_on_device);
 
+/* Statistics of the current state (Section 3.1.4, methodology): the
+ * compression ratio as dense bytes / store bytes (the x-factors of Section
+ * 3.2), the kept-coefficient count, the record encodings, and the FP64 totals
+ * that equation "conservation" keeps constant.  Error norms against an
+ * uncompressed run (equation "L2_error") are computed by the caller from
+ * lbmz_decompress_field of both contexts.  Errors: LBMZ_EINVAL (null out). */
 int lbmz_stats(lbmz_ctx* ctx, lbmz_stats_t* out);
 
 /* The per-field totals of lbmz_stats for all `count` = nfields fields. */

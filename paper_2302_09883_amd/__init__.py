@@ -7,8 +7,6 @@ from .lbmz import (  # noqa: F401
     Context,
     LbmzError,
     Net,
-    decode_records,
-    decode_records3,
     library,
     LIB_PATH,
 )

@@ -750,6 +750,10 @@ int lbmz_step(lbmz_ctx* c, int n) {
     rc = commit(c);
     if (rc) return rc;
   }
+  if (n == 0) {   // nothing to time: no event pair is recorded
+    c->ms_last = 0.0;
+    return LBMZ_OK;
+  }
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   if (c->reference) {
     for (int k = 0; k < n; ++k) {

@@ -399,123 +399,3 @@ def _current_stream():
     except Exception:   # noqa: BLE001
         pass
     return None
-
-
-def record_order(s: int) -> np.ndarray:
-    """Flat tile indices (y * s + x) in the record order of include/lbmz.h."""
-    p = s - 1 if s % 2 == 1 else s
-    yy, xx = np.meshgrid(np.arange(p), np.arange(p), indexing="ij")
-    parts = [(yy * s + xx).reshape(-1)]
-    if p != s:
-        parts += [np.arange(p) * s + p, p * s + np.arange(p), np.array([p * s + p])]
-    return np.concatenate(parts).astype(np.int64)
-
-
-def _e4m3_values(codes: np.ndarray) -> np.ndarray:
-    c = codes.astype(np.int64)
-    e = (c >> 3) & 15
-    m = (c & 7).astype(np.float64)
-    mag = np.where(e == 0, m * 2.0 ** -9, (1.0 + m / 8.0) * np.exp2(e - 7.0))
-    return np.where(c & 0x80, -mag, mag).astype(np.float32)
-
-
-def _decode_narrow(table, pool, s, values, levels):
-    npatch, nf = table.shape[:2]
-    nc = s * s
-    w = (nc + 63) // 64
-    order = record_order(s)
-    step = 1 << levels
-    sc = (s - 1) // step + 1
-    ns = sc * sc
-    cls = np.array([0 if i % step == 0 else (i & -i).bit_length() for i in range(s)])
-    band = (cls[:, None] * (levels + 1) + cls[None, :]).reshape(-1)[order]
-    by = 2 if values == "f16" else 1
-    buf = np.frombuffer(pool, dtype=np.uint8)
-    out = np.zeros((npatch, nf, s, s), dtype=np.float32)
-    for q in range(npatch):
-        for f in range(nf):
-            off = int(table[q, f, 0]) * 16
-            word = int(table[q, f, 1])
-            ndet = word & (MASK_BIT - 1)
-            occ = int(buf[off:off + 8].view("<u8")[0])
-            bands = [b for b in range(64) if (occ >> b) & 1]
-            scale = dict(zip(bands, buf[off + 8:off + 8 + 4 * len(bands)].view("<f4")))
-            hb = (8 + 4 * len(bands) + 7) // 8 * 8
-            sb = hb + (4 * ns + 7) // 8 * 8
-            vb = sb + (by * ndet + 7) // 8 * 8
-            samp = buf[off + hb:off + hb + 4 * ns].view("<f4").reshape(sc, sc)
-            out[q, f, ::step, ::step] = samp
-            if ndet == 0:
-                continue
-            raw = buf[off + sb:off + sb + by * ndet]
-            vals = raw.view("<f2").astype(np.float32) if values == "f16" else _e4m3_values(raw)
-            if word & MASK_BIT:
-                bits = np.unpackbits(buf[off + vb:off + vb + 8 * w], bitorder="little")[:nc].astype(bool)
-                ks = np.flatnonzero(bits)
-            else:
-                ks = buf[off + vb:off + vb + 2 * ndet].view("<u2").astype(np.int64)
-            sc_of = np.array([scale[int(b)] for b in band[ks]], dtype=np.float32)
-            flat = out[q, f].reshape(-1)
-            flat[order[ks]] = vals * sc_of
-    return out
-
-
-def decode_records(table: np.ndarray, pool: bytes, s: int, dtype, values: str = "f32",
-                   levels: int | None = None) -> np.ndarray:
-    """Coefficient tiles ``[npatch, nfields, s, s]`` from a store (host-side reader).
-
-    Reads the record layouts of include/lbmz.h; used to inspect what the
-    library wrote.  The narrow value formats need the level count and give
-    float32 tiles as read back (details times their subband scale).
-    """
-    if values != "f32":
-        if levels is None:
-            raise ValueError("narrow records need the level count")
-        return _decode_narrow(table, pool, s, values, levels)
-    dtype = np.dtype(dtype)
-    npatch, nf = table.shape[:2]
-    nc = s * s
-    w = (nc + 63) // 64
-    order = record_order(s)
-    seq = np.zeros((npatch, nf, nc), dtype=dtype)
-    buf = np.frombuffer(pool, dtype=np.uint8)
-    for q in range(npatch):
-        for f in range(nf):
-            off = int(table[q, f, 0]) * 16
-            word = int(table[q, f, 1])
-            nnz = word & (MASK_BIT - 1)
-            vb = (nnz * dtype.itemsize + 7) // 8 * 8
-            vals = buf[off:off + nnz * dtype.itemsize].view(dtype)
-            if word & MASK_BIT:
-                words = buf[off + vb:off + vb + 8 * w].view("<u8")
-                bits = np.unpackbits(words.view(np.uint8), bitorder="little")[:nc].astype(bool)
-                seq[q, f, bits] = vals
-            else:
-                idx = buf[off + vb:off + vb + 2 * nnz].view("<u2").astype(np.int64)
-                seq[q, f, idx] = vals
-    out = np.zeros_like(seq)
-    out[:, :, order] = seq
-    return out.reshape(npatch, nf, s, s)
-
-
-def decode_records3(table: np.ndarray, pool: bytes, s: int) -> np.ndarray:
-    """Coefficient tiles ``float32 [npatch, nfields, s, s, s]`` of a 3-D store
-    (record index k = x + s y + s^2 z; host-side reader of include/lbmz.h)."""
-    npatch, nf = table.shape[:2]
-    nc = s ** 3
-    w = (nc + 63) // 64
-    out = np.zeros((npatch, nf, nc), dtype=np.float32)
-    buf = np.frombuffer(pool, dtype=np.uint8)
-    for q in range(npatch):
-        for f in range(nf):
-            off = int(table[q, f, 0]) * 16
-            word = int(table[q, f, 1])
-            nnz = word & (MASK_BIT - 1)
-            vb = (4 * nnz + 7) // 8 * 8
-            vals = buf[off:off + 4 * nnz].view("<f4")
-            if word & MASK_BIT:
-                bits = np.unpackbits(buf[off + vb:off + vb + 8 * w], bitorder="little")[:nc].astype(bool)
-                out[q, f, bits] = vals
-            else:
-                out[q, f, buf[off + vb:off + vb + 2 * nnz].view("<u2").astype(np.int64)] = vals
-    return out.reshape(npatch, nf, s, s, s)

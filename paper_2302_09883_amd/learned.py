@@ -144,26 +144,37 @@ def train(x, y, epochs: int = 40, batch: int = 256, lr: float = 2e-3, seed: int 
     return net, hist
 
 
-def allocate(pred_err, pred_bytes, budget: float, fallback_index: int) -> np.ndarray:
-    """Per-patch candidate index by the greedy allocation described above."""
+def allocate(pred_err, pred_bytes, budget, fallback_index: int) -> np.ndarray:
+    """Per-patch candidate index by the greedy allocation described above.
+
+    A patch with any non-finite prediction is pinned to ``fallback_index`` and
+    left out of both the predicted total and the budget, so that the finite
+    patches are allocated exactly as they would be without it.  ``budget``
+    None means the predicted error of the fallback threshold on the finite
+    patches (the fixed method's own predicted error).
+    """
     npatch = pred_err.shape[0]
-    e = np.power(10.0, pred_err)
-    b = np.power(10.0, pred_bytes)
+    with np.errstate(over="ignore", invalid="ignore"):
+        e = np.power(10.0, np.asarray(pred_err, dtype=np.float64))
+        b = np.power(10.0, np.asarray(pred_bytes, dtype=np.float64))
     bad = ~(np.all(np.isfinite(e), axis=1) & np.all(np.isfinite(b), axis=1))
+    good = np.flatnonzero(~bad)
+    if budget is None:
+        budget = float(np.sum(e[good, fallback_index]))
     idx = np.full(npatch, K - 1, dtype=np.int64)
     idx[bad] = fallback_index
-    total = float(np.sum(e[np.arange(npatch), idx]))
+    total = float(np.sum(e[good, K - 1]))
     heap = []
 
     def push(q):
         i = idx[q]
-        if i == 0 or bad[q]:
+        if i == 0:
             return
         de = e[q, i] - e[q, i - 1]
         db = max(b[q, i - 1] - b[q, i], 1e-9)
         heapq.heappush(heap, (-(de / db), q, i))
 
-    for q in range(npatch):
+    for q in good:
         push(q)
     while total > budget and heap:
         _, q, i = heapq.heappop(heap)
@@ -202,8 +213,7 @@ def run_learned(net, n: int, seed: int, steps: int, fixed_eps: float, window: in
     while done < steps:
         pred = net.forward(c.features())
         pe, pb = pred[:, :K], pred[:, K:]
-        share = float(np.sum(np.power(10.0, pe[:, fb])))
-        idx = allocate(pe, pb, share, fb)
+        idx = allocate(pe, pb, None, fb)
         c.set_patch_eps(np.array([CANDIDATES[i] for i in idx], dtype=np.float64))
         chosen.append(np.bincount(idx, minlength=K).tolist())
         w = min(window, steps - done)

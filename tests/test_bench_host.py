@@ -42,3 +42,28 @@ def test_traffic_is_dropped_for_another_kernel(tmp_path, monkeypatch):
     assert bench.measured_traffic() is None
     prof.write_text(f"# header\nsource_digest {bench.kernel_source_digest()}\nbytes_per_launch 123\n")
     assert bench.measured_traffic() == 123
+
+
+def test_byte_model_matches_the_stated_per_update_figures():
+    # per lattice update at 2048^2: 78.2 B at density 1, 26.2 B at 0.3, 11.3 B at
+    # 0.1, 4.9 B at 0.03, 2.7 B at 0.01 (records read + written, halo, table)
+    npatch = (2048 // 64) ** 2
+    lups = 2048 * 2048
+    for rho, want in ((1.0, 78.2), (0.3, 26.2), (0.1, 11.3), (0.03, 4.9), (0.01, 2.7)):
+        assert abs(bench.bytes_model(rho, npatch) / lups - want) < 0.06, rho
+
+
+def test_fixed_error_ratio_interpolates_and_reports_saturation():
+    pts = [{"eps": 1e-5, "rel_l2": 1e-4, "ratio": 100.0}, {"eps": 1e-4, "rel_l2": 4e-4, "ratio": 200.0},
+           {"eps": 1e-3, "rel_l2": 8e-4, "ratio": 220.0}]
+    r = bench.cr_at_error(pts, 2e-4)
+    assert r["bracket_eps"] == [1e-5, 1e-4] and 100.0 < r["ratio"] < 200.0
+    r = bench.cr_at_error(pts, 1e-3)
+    assert r["bracket_eps"] is None and r["ratio"] == 220.0
+    assert bench.cr_at_error(pts, 1e-5)["ratio"] is None
+
+
+def test_cpu_baseline_harness_gives_the_oracle_result():
+    out = bench.cpu_baseline(steps=1, workers=2, n=128)
+    assert out["identical_results"] and out["cores"] == 2 and out["kind"] == "oracle"
+    assert out["value"] > 0 and out["one_core"]["value"] > 0 and out["cpu"]["nproc"] >= 1

@@ -51,7 +51,7 @@ def _oracle_state(n, seed, dtype=np.float64):
 
 
 def _tiles(ctx):
-    from paper_2302_09883_amd import decode_records3
+    from gpu_helpers import decode_records3
     table, pool = ctx.store()
     return decode_records3(table, pool, ctx.s), table, pool
 
@@ -89,10 +89,14 @@ def test_eps0_equals_reference_and_oracle(n, p, levels):
     assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(f))
 
 
-@pytest.mark.parametrize("density", [0.002, 0.3])
-def test_records_from_given_coefficients_are_the_oracles(density):
-    _say("3d records", density)
-    n, p, levels, eps = 32, 16, 3, 1e-3
+@pytest.mark.parametrize("n,p,density", [(32, 16, 0.002), (32, 16, 0.3), (64, 32, 0.045)])
+def test_records_from_given_coefficients_are_the_oracles(n, p, density):
+    """Byte-exact records; at P = 32 and density 0.045 every index list holds
+    about 1,100 - 2,200 entries, beyond the first workgroup-wide batch of the
+    expansion's list loads, so the prefetched entries and the tail loop of the
+    scatter are both exercised (the records are decompressed and compared)."""
+    _say("3d records", n, p, density)
+    levels, eps = 3, 1e-3
     g = O3.Geometry3(n, p, levels)
     rng = np.random.default_rng(5)
     coef = (rng.standard_normal((g.npatch, 19, g.s, g.s, g.s)) * 1e-2).astype(np.float32)
@@ -116,6 +120,14 @@ def test_records_from_given_coefficients_are_the_oracles(density):
     assert st["mask_records"] + st["list_records"] == g.npatch * 19
     if density < 0.01:
         assert st["list_records"] > 0
+    elif p == 32:
+        nnz = table[..., 1] & (O3.MASK_BIT - 1)
+        assert st["list_records"] == g.npatch * 19
+        assert 1024 < int(nnz.min()) and int(nnz.max()) < 2248
+        # the expansion of those lists: decompressed fields against the oracle's
+        want = twin.grid()
+        got_f = ctx.fields()
+        assert np.max(np.abs(got_f - want)) <= 2e-6 * np.max(np.abs(want))
     else:
         assert st["mask_records"] > 0
 
@@ -136,7 +148,7 @@ def test_one_step_from_common_state(n, p, levels, eps):
     got, _, _ = _tiles(ctx)
     want = twin.coef
     u = np.finfo(np.float32).eps
-    delta = 256 * u * float(np.max(np.abs(want)))
+    delta = 1e-5 * float(np.max(np.abs(want)))
     flip = (got != 0) != (want != 0)
     near = np.abs(np.abs(np.where(got != 0, got, want)) - twin.thr) <= delta
     assert np.all(near[flip]), int(flip.sum())
@@ -248,13 +260,13 @@ def test_full_size_sampled_patches():
         got = np.stack([O3.decode_record3(pool2, int(table2[q, f, 0]), int(table2[q, f, 1]), g.s, np.float32)
                         for f in range(19)])
         w = want[q]
-        delta = 256 * u * float(np.max(np.abs(w)))
+        delta = 1e-5 * float(np.max(np.abs(w)))
         flip = (got != 0) != (w != 0)
         near = np.abs(np.abs(np.where(got != 0, got, w)) - thr) <= delta
         assert np.all(near[flip]), (q, int(flip.sum()))
         assert np.max(np.abs(np.where(flip, 0.0, got - w))) <= delta, q
         assert 0 < np.count_nonzero(got) < got.size
-    assert ctx.stats()["regrows"] >= 0
+    assert ctx.stats()["regrows"] == 0
 
 
 def test_single_patch_grid_is_its_own_neighbour():

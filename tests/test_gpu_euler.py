@@ -85,7 +85,7 @@ def test_one_step_from_common_state(eps):
     ctx.put_store(table, pool)
     ctx.step(1)
     twin.step(1)
-    from paper_2302_09883_amd import decode_records
+    from gpu_helpers import decode_records
     t2, p2 = ctx.store()
     got = decode_records(t2, p2, twin.g.s, np.float32)
     want = twin.coef

@@ -38,7 +38,7 @@ def _lbm(n=256, eps=1e-4, p=64, levels=5, **kw):
 
 
 def _tiles(ctx):
-    from paper_2302_09883_amd import decode_records
+    from gpu_helpers import decode_records
     table, pool = ctx.store()
     return decode_records(table, pool, ctx.s, ctx.np_dtype), table
 

@@ -40,7 +40,7 @@ def _neighbourhood(q, npx):
 @pytest.mark.parametrize("eps", [1e-4, 0.0])
 def test_sampled_patches_one_step_at_full_size(eps):
     _say("full size sampled", eps)
-    from paper_2302_09883_amd import decode_records
+    from gpu_helpers import decode_records
     ctx = make_ctx(N, "d2q9_bgk", "f32", P, "bl53", L, eps)
     rho, ux, uy = shear_layer_macroscopic(N, seed=0)
     ctx.set_macroscopic(*(a.astype(np.float32) for a in (rho, ux, uy)))
@@ -62,7 +62,7 @@ def test_sampled_patches_one_step_at_full_size(eps):
     got = decode_records(t2[SAMPLE], p2, g.s, np.float32)
     u = np.finfo(np.float32).eps
     scale = float(np.max(np.abs(lossy[SAMPLE])))
-    delta = 256 * u * scale
+    delta = 1e-5 * scale   # the stated float32 bar, 1e-5 of the field scale
     thr = np.broadcast_to(run.thr, want.shape)
     kg, kw = got != 0, want != 0
     flip = kg != kw

@@ -91,7 +91,12 @@ def test_gradients_match_oracle():
         a = g[off:off + size]
         b = wg[name].reshape(-1)
         off += size
-        assert np.linalg.norm(a - b) <= 2e-3 * np.linalg.norm(b) + 1e-7, name
+        # per parameter, relative to the tensor's largest gradient (float32
+        # accumulation against float64; a ReLU whose input sits within
+        # rounding of 0 may switch, which moves a few entries by ~1e-4)
+        err = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+        print(f"[grad] {name}: max |gpu - oracle| / max |oracle| = {err:.2e}", flush=True)
+        assert err <= 1e-3, name
 
 
 def test_adam_step_matches_oracle():
@@ -137,7 +142,7 @@ def _macro(n, seed):
 
 
 def test_per_patch_thresholds_one_step_from_common_state():
-    from paper_2302_09883_amd import decode_records
+    from gpu_helpers import decode_records
     _say("per-patch eps")
     n, p, levels = 256, 64, 5
     rng = np.random.default_rng(13)
@@ -158,7 +163,7 @@ def test_per_patch_thresholds_one_step_from_common_state():
     got = decode_records(t2, p2, g.s, np.float32)
     want = twin.coef
     u = np.finfo(np.float32).eps
-    delta = 256 * u * float(np.max(np.abs(twin.grid())))
+    delta = 1e-5 * float(np.max(np.abs(twin.grid())))
     flip = (got != 0) != (want != 0)
     near = np.abs(np.abs(np.where(got != 0, got, want)) - twin.thr) <= delta
     assert np.all(near[flip]), int(flip.sum())
@@ -170,7 +175,7 @@ def test_per_patch_thresholds_one_step_from_common_state():
 
 
 def test_features_are_the_stored_coefficients_at_stride_8():
-    from paper_2302_09883_amd import decode_records
+    from gpu_helpers import decode_records
     _say("features")
     n = 256
     ctx = make_ctx(n, "d2q9_bgk", "f32", 64, "bl53", 5, 1e-4)

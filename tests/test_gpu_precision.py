@@ -119,7 +119,7 @@ def test_narrow_store_reads_back(fmt, geom):
     assert np.max(np.abs(got - want)) <= 2e-6 * np.max(np.abs(want))
     t2, p2 = ctx.store()
     assert np.array_equal(t2, table) and p2 == pool
-    from paper_2302_09883_amd import decode_records
+    from gpu_helpers import decode_records
     tiles = decode_records(table, pool, twin.g.s, np.float32, values=fmt, levels=levels)
     assert np.array_equal(tiles.view(np.uint32), twin.coef.view(np.uint32))
 
@@ -130,7 +130,7 @@ def test_narrow_store_reads_back(fmt, geom):
 def test_narrow_one_step_from_common_state(fmt, geom, eps):
     n, scheme, p, wavelet, levels = geom
     _say("narrow one-step", fmt, geom, eps)
-    from paper_2302_09883_amd import decode_records
+    from gpu_helpers import decode_records
     ctx = make_ctx(n, scheme, "f32", p, wavelet, levels, eps, values=fmt)
     twin = _twin(n, scheme, p, wavelet, levels, eps, fmt)
     twin.set_grid(_state(n, scheme, seed=3))
@@ -151,11 +151,11 @@ def test_narrow_one_step_from_common_state(fmt, geom, eps):
     # codes: one step of the narrow format's rounding at the subband scale
     rel = 2.0 ** -10 if fmt == "f16" else 2.0 ** -3
     d = np.abs(got.astype(np.float64) - want)
-    bound = rel * np.maximum(np.abs(want), np.abs(got)) + 256 * u * scale + 2 * twin.thr.max()
+    bound = rel * np.maximum(np.abs(want), np.abs(got)) + 1e-5 * scale + 2 * twin.thr.max()
     assert np.all(d <= bound)
     # the samples are stored exactly: compare them to round-off
     sb = Q.subband_table(twin.g.s, levels) == 0
-    assert np.max(np.abs(got[..., sb] - want[..., sb])) <= 256 * u * scale
+    assert np.max(np.abs(got[..., sb] - want[..., sb])) <= 1e-5 * scale
 
 
 @pytest.mark.parametrize("fmt", Q.FORMATS)
