@@ -333,6 +333,25 @@ int lbmz_net_gradients(lbmz_net* net, const float* x, const float* t, int batch,
 /* One Adam step on the batch; *loss (may be null) is the loss before the step. */
 int lbmz_net_train_step(lbmz_net* net, const float* x, const float* t, int batch, float lr, float* loss,
                         int on_device);
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc.  The same
+ * gradients and loss as lbmz_net_gradients, computed by the same kernels, but
+ * the per-workgroup partial sums (the workspace lbmz_net_gradients allocates
+ * and grows with the batch) live in one fixed device array of
+ * LBMZ_NET_SCRATCH_BYTES per GPU, set up by lbmz_net_create and held until
+ * the process ends; this call allocates nothing and frees nothing.
+ * x [batch][9][8][8], t [batch][K], grad [param_count] and loss [1] are
+ * float32 device pointers on the network's device; grad and *loss are
+ * written.  The call is asynchronous on the network's stream.  The workspace
+ * needs ceil(batch / 16) * (4 * param_count) bytes, rounded up to 256, plus
+ * 4 * ceil(batch / 16): a batch above that (3104 samples at K = 12) returns
+ * LBMZ_EINVAL with the limit in lbmz_net_last_error.  Every call on one GPU
+ * shares its array (each call fully rewrites the part it reads), so calls
+ * that overlap in time on one GPU -- from any network or stream -- race. */
+#define LBMZ_NET_SCRATCH_BYTES (16 * 1024 * 1024)
+int lbmz_net_gradients_noalloc(lbmz_net* net, const float* x, const float* t, int batch, float* grad,
+                               float* loss);
 const char* lbmz_net_last_error(const lbmz_net* net);
 void lbmz_net_destroy(lbmz_net* net);
 

@@ -15,7 +15,9 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -282,13 +284,34 @@ __global__ void net_round_kernel(const float* __restrict__ master, uint16_t* __r
   if (j < np) wbf[j] = to_bf16(master[j]);
 }
 
+// Loss of a batch from the per-workgroup sums of squared differences: the
+// same double-precision sum in block order as the host reduction of
+// lbmz_net_gradients, so that both entry points give the same float.
+__global__ void net_loss_kernel(const float* __restrict__ loss_part, int nblocks, double denom,
+                                float* __restrict__ loss) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double l = 0.0;
+    for (int b = 0; b < nblocks; ++b) l += (double)loss_part[b];
+    *loss = (float)(l / denom);
+  }
+}
+
 }  // namespace lbmz_net_impl
+
+// Workspace of lbmz_net_gradients_noalloc: the per-workgroup partial
+// gradient sums [blocks][np] and, from the next 256-byte boundary, the
+// per-workgroup loss sums [blocks].  One copy per GPU, for the life of the
+// process.  In host code this name is only a stand-in for the symbol: the
+// device address of each GPU's copy comes from hipGetSymbolAddress (below)
+// and is the only value passed to kernels.
+static __device__ __align__(256) unsigned char scratch[LBMZ_NET_SCRATCH_BYTES];
 
 using namespace lbmz_net_impl;
 
 struct lbmz_net {
   int k = 0, np = 0;
   int step = 0;
+  int device = 0;               // device current at creation (its parameters live there)
   hipStream_t stream = nullptr;
   float* master = nullptr;
   uint16_t* wbf = nullptr;
@@ -303,6 +326,29 @@ struct lbmz_net {
 };
 
 namespace {
+
+// Device address of `scratch` per device ordinal, set once per device by the
+// first lbmz_net_create on it (with that device current).
+constexpr int MAX_DEVICES = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+hipError_t scratch_setup(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = p;
+  return hipSuccess;
+}
+
+void* scratch_of(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
 
 int net_fail(lbmz_net* n, int code, const char* msg) {
   if (n) n->err = msg;
@@ -385,6 +431,10 @@ int lbmz_net_create(int k, lbmz_net** out) {
   if (!n) return LBMZ_ENOMEM;
   n->k = k;
   n->np = nparams(k);
+  if (hipGetDevice(&n->device) != hipSuccess || scratch_setup(n->device) != hipSuccess) {
+    delete n;
+    return LBMZ_EDEVICE;
+  }
   const size_t fb = (size_t)n->np * sizeof(float);
   if (hipMalloc(&n->master, fb) != hipSuccess || hipMalloc(&n->wbf, (size_t)n->np * 2) != hipSuccess ||
       hipMalloc(&n->m, fb) != hipSuccess || hipMalloc(&n->v, fb) != hipSuccess ||
@@ -481,19 +531,55 @@ int lbmz_net_train_step(lbmz_net* n, const float* x, const float* t, int batch, 
   return LBMZ_OK;
 }
 
+int lbmz_net_gradients_noalloc(lbmz_net* n, const float* x, const float* t, int batch, float* grad, float* loss) {
+  if (!n) return LBMZ_EINVAL;
+  if (!x || !t || !grad || !loss) return net_fail(n, LBMZ_EINVAL, "null device pointer");
+  if (batch <= 0) return net_fail(n, LBMZ_EINVAL, "batch must be > 0");
+  // workspace bytes of b workgroups: partial sums, 256-byte boundary, loss sums
+  auto need_of = [n](long long b) {
+    const size_t part_bytes = (size_t)b * (size_t)n->np * sizeof(float);
+    return ((part_bytes + 255u) & ~(size_t)255u) + (size_t)b * sizeof(float);
+  };
+  const int blocks = (batch + SPW - 1) / SPW;
+  const size_t need = need_of(blocks);
+  if (need > (size_t)LBMZ_NET_SCRATCH_BYTES) {
+    long long maxb = (long long)LBMZ_NET_SCRATCH_BYTES / ((long long)n->np * 4);
+    while (maxb > 0 && need_of(maxb) > (size_t)LBMZ_NET_SCRATCH_BYTES) --maxb;
+    char msg[200];
+    snprintf(msg, sizeof msg, "batch %d needs %zu bytes of gradient workspace, above the fixed %d (batch <= %lld)",
+             batch, need, (int)LBMZ_NET_SCRATCH_BYTES, maxb * SPW);
+    return net_fail(n, LBMZ_EINVAL, msg);
+  }
+  const size_t lp_off = (((size_t)blocks * (size_t)n->np * sizeof(float)) + 255u) & ~(size_t)255u;
+  uint8_t* base = static_cast<uint8_t*>(scratch_of(n->device));
+  if (!base) return net_fail(n, LBMZ_ESTATE, "no workspace address for the network's device");
+  float* part = reinterpret_cast<float*>(base);
+  float* loss_part = reinterpret_cast<float*>(base + lp_off);
+  hipLaunchKernelGGL(net_grad_kernel, dim3(blocks), dim3(NT), 0, n->stream, n->wbf, x, t, batch, n->k, part,
+                     loss_part);
+  NETCHK(n, hipGetLastError());
+  hipLaunchKernelGGL(net_reduce_kernel, dim3((n->np + 255) / 256), dim3(256), 0, n->stream, part, blocks, n->np,
+                     grad);
+  NETCHK(n, hipGetLastError());
+  hipLaunchKernelGGL(net_loss_kernel, dim3(1), dim3(64), 0, n->stream, loss_part, blocks,
+                     (double)batch * n->k, loss);
+  NETCHK(n, hipGetLastError());
+  return LBMZ_OK;
+}
+
 const char* lbmz_net_last_error(const lbmz_net* n) { return n ? n->err.c_str() : "null network"; }
 
 void lbmz_net_destroy(lbmz_net* n) {
   if (!n) return;
   (void)hipDeviceSynchronize();
-  hipFree(n->master);
-  hipFree(n->wbf);
-  hipFree(n->m);
-  hipFree(n->v);
-  hipFree(n->grad);
-  hipFree(n->part);
-  hipFree(n->loss_part);
-  hipFree(n->io);
+  (void)hipFree(n->master);
+  (void)hipFree(n->wbf);
+  (void)hipFree(n->m);
+  (void)hipFree(n->v);
+  (void)hipFree(n->grad);
+  (void)hipFree(n->part);
+  (void)hipFree(n->loss_part);
+  (void)hipFree(n->io);
   delete n;
 }
 

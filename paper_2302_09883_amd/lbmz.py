@@ -103,6 +103,7 @@ def library() -> ct.CDLL:
         "lbmz_net_forward": ([vp, vp, ct.c_int, vp, ct.c_int], ct.c_int),
         "lbmz_net_gradients": ([vp, vp, vp, ct.c_int, vp, P(ct.c_float), ct.c_int], ct.c_int),
         "lbmz_net_train_step": ([vp, vp, vp, ct.c_int, ct.c_float, P(ct.c_float), ct.c_int], ct.c_int),
+        "lbmz_net_gradients_noalloc": ([vp, vp, vp, ct.c_int, vp, vp], ct.c_int),
         "lbmz_net_last_error": ([vp], ct.c_char_p),
         "lbmz_net_destroy": ([vp], None),
         "lbmz_destroy": ([vp], None),
@@ -381,6 +382,17 @@ class Net:
         self._check(self._lib.lbmz_net_gradients(self._h, ct.c_void_p(xa.ctypes.data), ct.c_void_p(ta.ctypes.data),
                                                  xa.shape[0], ct.c_void_p(g.ctypes.data), ct.byref(loss), 0))
         return g, float(loss.value)
+
+    def gradients_noalloc(self, x, t, grad, loss):
+        """lbmz_net_gradients_noalloc: x, t, grad and loss are contiguous float32
+        device tensors ([B][9][8][8], [B][K], [nparams], [1]); asynchronous on
+        the network's stream."""
+        for a in (x, t, grad, loss):
+            if not (_is_torch(a) and a.is_cuda and a.is_contiguous()):
+                raise ValueError("device tensors expected")
+        self._check(self._lib.lbmz_net_gradients_noalloc(self._h, ct.c_void_p(x.data_ptr()), ct.c_void_p(t.data_ptr()),
+                                                         int(x.shape[0]), ct.c_void_p(grad.data_ptr()),
+                                                         ct.c_void_p(loss.data_ptr())))
 
     def train_step(self, x, t, lr: float) -> float:
         xp, xb, xdev, xk = _buffer(x, np.float32)
