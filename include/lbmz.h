@@ -123,7 +123,14 @@ typedef enum { LBMZ_THR_CAPPED = 0, LBMZ_THR_CONSTANT = 1, LBMZ_THR_ACCUM = 2 } 
 typedef enum {
   LBMZ_VALUES_F32 = 0,   /* every kept coefficient in the state's dtype */
   LBMZ_VALUES_F16 = 1,   /* float32 samples, binary16 details */
-  LBMZ_VALUES_E4M3 = 2   /* float32 samples, E4M3 details */
+  LBMZ_VALUES_E4M3 = 2,  /* float32 samples, E4M3 details */
+  /* float32 samples; per record, E4M3 details when E4M3's rounding bound
+   * max(2^-4 m_b, 2^(k_b - 10)) at the largest kept magnitude m_b of every
+   * occupied subband b (E4M3 scale 2^k_b) is at most half of that subband's
+   * threshold (Section 2.2), binary16 details otherwise: the quantisation
+   * then adds at most half of the error the threshold already allows per
+   * coefficient.  At eps = 0 every record with a detail is binary16. */
+  LBMZ_VALUES_E4M3_BOUNDED = 3
 } lbmz_values;
 
 /* Patch decomposition: p[0] = p[1] = cells per patch side, a power of two
@@ -249,9 +256,11 @@ int lbmz_set_macroscopic3(lbmz_ctx* ctx, const void* rho, const void* ux, const 
  *   either their u16 indices k (when 2 nnz < 8 W) or W u64 mask words (bit
  *   k%64 of word k/64), zero padding to a multiple of 16 bytes.  The offset
  *   table count is nnz.
- * Narrow records (LBMZ_VALUES_F16 / E4M3): u64 OCC with bit b set when
- *   subband b = cy (L + 1) + cx holds a kept detail (cx, cy: 0 for a sample
- *   index, else the detail level, 1 = finest); one float32 scale 2^k per set
+ * Narrow records (LBMZ_VALUES_F16 / E4M3 / E4M3_BOUNDED): u64 OCC with bit b
+ *   set when subband b = cy (L + 1) + cx holds a kept detail (cx, cy: 0 for a
+ *   sample index, else the detail level, 1 = finest), and for E4M3_BOUNDED
+ *   bit 63 set when the record's codes are E4M3 (else binary16, scales and
+ *   codes of that format); one float32 scale 2^k per set
  *   bit, in increasing b, where 2^k is the smallest power of two with
  *   max |detail| <= 65504 (F16) or 448 (E4M3) times 2^k; zero pad to 8;
  *   float32 samples of all SC x SC sample positions (SC = (s-1)/2^L + 1),

@@ -691,7 +691,7 @@ class CompressedRun:
         if self.values == "f32":
             return c
         from .lbmz_precision import quantize_tiles
-        return quantize_tiles(c, self.g.levels, self.values)
+        return quantize_tiles(c, self.g.levels, self.values, self.thr)
 
     def decompress_tiles(self, coef: np.ndarray | None = None) -> np.ndarray:
         c = self.coef if coef is None else coef
@@ -732,7 +732,7 @@ class CompressedRun:
     def store(self):
         if self.values != "f32":
             from .lbmz_precision import encode_store_q
-            return encode_store_q(self.raw, self.g.levels, self.values)
+            return encode_store_q(self.raw, self.g.levels, self.values, self.thr)
         return encode_store(self.coef)
 
     def nnz(self) -> np.ndarray:
@@ -749,7 +749,7 @@ class CompressedRun:
         ncoef = self.g.s * self.g.s
         if self.values != "f32":
             from .lbmz_precision import store_bytes_q
-            return store_bytes_q(self.kept.astype(np.float32), self.g.levels, self.values)
+            return store_bytes_q(self.raw.astype(np.float32), self.g.levels, self.values, self.thr)
         tot = 0
         for v in self.nnz().reshape(-1):
             tot += record_layout(int(v), ncoef, self.dtype.itemsize)[3]

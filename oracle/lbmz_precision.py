@@ -22,6 +22,19 @@ Narrow value formats:
   that definition (the value of every code), rounding to the nearest value,
   ties to the even code.
 
+* ``"e4m3b"``: E4M3 where it is error-bounded, binary16 elsewhere, chosen per
+  record.  A kept detail c read back from E4M3 with scale 2**k is off by at
+  most max(2**-4 |c|, 2**(k - 10)) (half a unit of the 3-bit mantissa in the
+  normal range, half the subnormal spacing 2**-9 below it).  A record is
+  stored in E4M3 when, for every subband holding a kept detail, that bound
+  at the subband's largest kept magnitude m_b and E4M3 scale 2**k_b is at
+  most half the subband's threshold (:data:`E4M3B_FRACTION` x thr_b): the
+  quantisation then adds less than half of the error the threshold already
+  accepts for a dropped detail.  Otherwise the whole record is binary16 (as
+  is every record at eps = 0, where the threshold is zero).  Bit 63 of OCC
+  is set for an E4M3 record.  The threshold of a subband is the one the
+  thresholding used (one value per subband for every rule).
+
 Per-subband scales: a detail at tile position (y, x) belongs to subband
 ``(cy, cx)``, the per-dimension classes (0 for a sample index, else the
 detail level, 1 = finest) of the thresholding; its index is
@@ -52,9 +65,11 @@ import numpy as np
 
 from .lbmz_oracle import MASK_BIT, index_levels, record_order, _align
 
-FORMATS = ("f16", "e4m3")
+FORMATS = ("f16", "e4m3", "e4m3b")
 FMT_MAX = {"f16": 65504.0, "e4m3": 448.0}
 FMT_BYTES = {"f16": 2, "e4m3": 1}
+E4M3B_FRACTION = 0.5          # E4M3 rounding bound allowed, as a fraction of the subband threshold
+OCC_E4M3_BIT = 1 << 63        # "e4m3b" records: OCC bit of an E4M3 record
 
 
 # ---------------------------------------------------------------------------
@@ -161,15 +176,48 @@ def sample_positions(s: int, levels: int):
     return [(y, x) for y in idx for x in idx], len(idx)
 
 
-def quantize_tile(tile: np.ndarray, levels: int, fmt: str):
+def e4m3_bound_holds(tile: np.ndarray, levels: int, thr: np.ndarray) -> bool:
+    """The "e4m3b" choice for one thresholded float32 tile with its threshold
+    table ``thr`` ([s, s], float32): True when every occupied subband's E4M3
+    rounding bound is at most E4M3B_FRACTION times its threshold."""
+    t = np.asarray(tile, dtype=np.float32)
+    s = t.shape[-1]
+    sb = subband_table(s, levels)
+    th = np.broadcast_to(np.asarray(thr, dtype=np.float32), t.shape)
+    for b in range(1, (levels + 1) ** 2):
+        sel = (sb == b) & (t != 0)
+        if not np.any(sel):
+            continue
+        m = float(np.max(np.abs(t[sel])))
+        k = int(np.log2(float(pow2_scale(m, "e4m3"))))
+        bound = max(m * 2.0 ** -4, 2.0 ** (k - 10))
+        thr_b = float(th[sb == b][0])
+        if not bound <= E4M3B_FRACTION * thr_b:
+            return False
+    return True
+
+
+def effective_format(tile: np.ndarray, levels: int, fmt: str, thr=None) -> str:
+    """The code format a record of this tile uses: ``fmt`` itself, or for
+    ``"e4m3b"`` "e4m3" or "f16" by :func:`e4m3_bound_holds` (``thr`` needed)."""
+    if fmt != "e4m3b":
+        return fmt
+    if thr is None:
+        raise ValueError("the e4m3b format needs the threshold table")
+    return "e4m3" if e4m3_bound_holds(tile, levels, thr) else "f16"
+
+
+def quantize_tile(tile: np.ndarray, levels: int, fmt: str, thr=None):
     """Stored representation of one thresholded float32 tile.
 
     Returns ``(deq, scales, occ)``: the tile as read back (samples unchanged,
     kept details quantised with their subband scale), the per-subband scales
-    (index b -> float32, only for occupied subbands) and the occupancy mask.
+    (index b -> float32, only for occupied subbands) and the occupancy mask
+    (with OCC_E4M3_BIT for an E4M3 "e4m3b" record).
     """
     t = np.asarray(tile, dtype=np.float32)
     s = t.shape[-1]
+    eff = effective_format(t, levels, fmt, thr)
     sb = subband_table(s, levels)
     out = t.copy()
     scales = {}
@@ -178,21 +226,33 @@ def quantize_tile(tile: np.ndarray, levels: int, fmt: str):
         sel = (sb == b) & (t != 0)
         if not np.any(sel):
             continue
-        sc = pow2_scale(float(np.max(np.abs(t[sel]))), fmt)
+        sc = pow2_scale(float(np.max(np.abs(t[sel]))), eff)
         scales[b] = sc
         occ |= 1 << b
-        q = quantize(t[sel] / sc, fmt)
-        out[sel] = dequantize(q, fmt) * sc
+        q = quantize(t[sel] / sc, eff)
+        out[sel] = dequantize(q, eff) * sc
+    if fmt == "e4m3b" and eff == "e4m3":
+        occ |= OCC_E4M3_BIT
     return out, scales, occ
 
 
-def quantize_tiles(coef: np.ndarray, levels: int, fmt: str) -> np.ndarray:
-    """:func:`quantize_tile` applied to every tile of ``[..., s, s]``."""
+def _tile_thresholds(thr, shape):
+    """Per-tile threshold tables for tiles of ``shape`` = [..., s, s] (None kept)."""
+    if thr is None:
+        return None
+    t = np.broadcast_to(np.asarray(thr, dtype=np.float32), shape)
+    return t.reshape(-1, shape[-2], shape[-1])
+
+
+def quantize_tiles(coef: np.ndarray, levels: int, fmt: str, thr=None) -> np.ndarray:
+    """:func:`quantize_tile` applied to every tile of ``[..., s, s]``; ``thr``
+    broadcasts against the tiles (the "e4m3b" choice needs it)."""
     c = np.asarray(coef, dtype=np.float32)
     flat = c.reshape(-1, c.shape[-2], c.shape[-1])
+    th = _tile_thresholds(thr, c.shape)
     out = np.empty_like(flat)
     for i in range(flat.shape[0]):
-        out[i] = quantize_tile(flat[i], levels, fmt)[0]
+        out[i] = quantize_tile(flat[i], levels, fmt, None if th is None else th[i])[0]
     return out.reshape(c.shape)
 
 
@@ -211,13 +271,15 @@ def record_layout_q(ndet: int, nocc: int, ncoef: int, nsamp: int, fmt: str):
     return is_mask, hb, sb, vb, _align(vb + mb, 16)
 
 
-def encode_record_q(tile: np.ndarray, levels: int, fmt: str):
-    """``(bytes, ndet, is_mask)`` of one thresholded float32 tile."""
+def encode_record_q(tile: np.ndarray, levels: int, fmt: str, thr=None):
+    """``(bytes, ndet, is_mask)`` of one thresholded float32 tile (``thr``: its
+    threshold table, needed by "e4m3b")."""
     t = np.asarray(tile, dtype=np.float32)
     s = t.shape[-1]
     ncoef = s * s
     sb = subband_table(s, levels)
-    _, scales, occ = quantize_tile(t, levels, fmt)
+    _, scales, occ = quantize_tile(t, levels, fmt, thr)
+    fmt = effective_format(t, levels, fmt, thr)
     order = record_order(s)
     flat = t.reshape(-1)
     sbf = sb.reshape(-1)
@@ -255,6 +317,9 @@ def decode_record_q(buf: bytes, off16: int, word: int, s: int, levels: int, fmt:
     is_mask = bool(word & MASK_BIT)
     base = 16 * off16
     occ = int(np.frombuffer(buf, dtype="<u8", count=1, offset=base)[0])
+    if fmt == "e4m3b":
+        fmt = "e4m3" if occ & OCC_E4M3_BIT else "f16"
+        occ &= ~OCC_E4M3_BIT
     bands = [b for b in range(64) if (occ >> b) & 1]
     scl = np.frombuffer(buf, dtype="<f4", count=len(bands), offset=base + 8)
     scale_of = {b: np.float32(v) for b, v in zip(bands, scl)}
@@ -286,15 +351,18 @@ def decode_record_q(buf: bytes, off16: int, word: int, s: int, levels: int, fmt:
     return out
 
 
-def encode_store_q(coef: np.ndarray, levels: int, fmt: str):
-    """Offset table and pool of ``[npatch, m, s, s]`` thresholded float32 tiles (serial placement)."""
+def encode_store_q(coef: np.ndarray, levels: int, fmt: str, thr=None):
+    """Offset table and pool of ``[npatch, m, s, s]`` thresholded float32 tiles
+    (serial placement); ``thr`` broadcasts against the tiles ("e4m3b")."""
     npatch, m = coef.shape[0], coef.shape[1]
+    th = _tile_thresholds(thr, coef.shape)
     table = np.zeros((npatch, m, 2), dtype=np.uint32)
     parts = []
     off = 0
     for q in range(npatch):
         for f in range(m):
-            rec, ndet, is_mask = encode_record_q(coef[q, f], levels, fmt)
+            rec, ndet, is_mask = encode_record_q(coef[q, f], levels, fmt,
+                                                 None if th is None else th[q * m + f])
             table[q, f, 0] = off // 16
             table[q, f, 1] = ndet | (MASK_BIT if is_mask else 0)
             parts.append(rec)
@@ -311,9 +379,11 @@ def decode_store_q(table: np.ndarray, pool: bytes, s: int, levels: int, fmt: str
     return out
 
 
-def store_bytes_q(coef: np.ndarray, levels: int, fmt: str) -> int:
-    """Bytes of the narrow store of thresholded tiles: all records plus the offset table."""
+def store_bytes_q(coef: np.ndarray, levels: int, fmt: str, thr=None) -> int:
+    """Bytes of the narrow store of thresholded tiles: all records plus the
+    offset table ("e4m3b" needs the kept values and ``thr``)."""
     npatch, m, s = coef.shape[0], coef.shape[1], coef.shape[-1]
+    th = _tile_thresholds(thr, coef.shape)
     sb = subband_table(s, levels)
     nsamp = len(sample_positions(s, levels)[0])
     tot = 0
@@ -322,5 +392,6 @@ def store_bytes_q(coef: np.ndarray, levels: int, fmt: str) -> int:
             t = coef[q, f]
             det = (sb != 0) & (t != 0)
             nocc = len(set(sb[det].tolist()))
-            tot += record_layout_q(int(det.sum()), nocc, s * s, nsamp, fmt)[4]
+            eff = effective_format(t, levels, fmt, None if th is None else th[q * m + f])
+            tot += record_layout_q(int(det.sum()), nocc, s * s, nsamp, eff)[4]
     return tot + npatch * m * 8

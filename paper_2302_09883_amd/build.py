@@ -29,6 +29,8 @@ SOURCES = [
     "lbmz_inst_f32_euler.hip",
     "lbmz_net.hip",
     "lbmz_d3q19.hip",
+    "lbmz_inst_f32_e4m3b_lbm.hip",
+    "lbmz_inst_f32_e4m3b_fv.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

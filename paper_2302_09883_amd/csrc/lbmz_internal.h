@@ -10,8 +10,10 @@ enum Wavelet : int { W_HAAR = 0, W_BL53 = 1 };
 enum SchemeKind : int { S_FV = 0, S_LBM = 1, S_EULER = 2, S_LBM3 = 3 };   // S_LBM3: D3Q19 on 3-D grids
 enum Rule : int { R_CAPPED = 0, R_CONSTANT = 1, R_ACCUM = 2 };
 // How the values of a record are stored: float32 (every kept coefficient), or
-// float32 samples plus binary16 / OCP E4M3 details with per-subband scales.
-enum ValueFormat : int { VF_F32 = 0, VF_F16 = 1, VF_E4M3 = 2 };
+// float32 samples plus binary16 / OCP E4M3 details with per-subband scales;
+// VF_E4M3B chooses per record: E4M3 where its rounding error is bounded by
+// half of every occupied subband's threshold, binary16 otherwise.
+enum ValueFormat : int { VF_F32 = 0, VF_F16 = 1, VF_E4M3 = 2, VF_E4M3B = 3 };
 
 // Modes of the auxiliary (not time-critical) patch kernel.
 enum AuxMode : int {

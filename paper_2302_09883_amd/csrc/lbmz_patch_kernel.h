@@ -107,6 +107,7 @@ struct NarrowLds {
   uint32_t hb[C::M];                     // byte offset of the samples in the record
   uint32_t sb[C::M];                     // byte offset of the detail values
   uint16_t wpre[C::M][C::W + 1];         // bitmask records: set bits before each word
+  uint32_t e4[C::M];                     // 1: the record's codes are E4M3, 0: binary16
 };
 struct NoLds {};
 

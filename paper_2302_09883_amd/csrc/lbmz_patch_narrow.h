@@ -2,7 +2,9 @@
 // with one power-of-two scale per subband (included by lbmz_patch_kernel.h).
 //
 // Layout of one (patch, field) record in a narrow format (little-endian):
-//   u64 OCC (bit b: subband b = cy * (L + 1) + cx holds a kept detail),
+//   u64 OCC (bit b: subband b = cy * (L + 1) + cx holds a kept detail; with
+//   the bounded E4M3 format bit 63 marks a record of E4M3 codes, a record
+//   without it holds binary16 codes),
 //   one float32 scale 2^k per set bit of OCC (increasing b), pad to 8;
 //   float32 samples of every sample position, slot (y >> L) * SC + (x >> L)
 //   with SC samples per side, pad to 8;
@@ -76,20 +78,38 @@ __device__ __forceinline__ int scale_exp(float m) {
   return k < -126 ? -126 : k;
 }
 
+// Codes of one record: e4 selects E4M3 (1 byte), else binary16 (2 bytes).
+// For the fixed formats e4 is a compile-time constant (fixed_e4) and the
+// selection folds away; the bounded format decides it per record.
 template <int VF>
-__device__ __forceinline__ uint32_t q_enc(float c, int k) { return VFmt<VF>::enc(ldexpf(c, -k)); }
-template <int VF>
-__device__ __forceinline__ float q_dec(uint32_t code, int k) { return ldexpf(VFmt<VF>::dec(code), k); }
+__device__ __forceinline__ constexpr bool fixed_e4() { return VF == VF_E4M3; }
 
-template <int VF>
-__device__ __forceinline__ void q_store(uint8_t* base, int i, uint32_t code) {
-  if constexpr (VFmt<VF>::BYTES == 2) reinterpret_cast<uint16_t*>(base)[i] = (uint16_t)code;
-  else base[i] = (uint8_t)code;
+__device__ __forceinline__ uint32_t q_enc(bool e4, float c, int k) {
+  const float x = ldexpf(c, -k);
+  return e4 ? VFmt<VF_E4M3>::enc(x) : VFmt<VF_F16>::enc(x);
 }
-template <int VF>
-__device__ __forceinline__ uint32_t q_load(const uint8_t* base, int i) {
-  if constexpr (VFmt<VF>::BYTES == 2) return reinterpret_cast<const uint16_t*>(base)[i];
-  else return base[i];
+__device__ __forceinline__ float q_dec(bool e4, uint32_t code, int k) {
+  return ldexpf(e4 ? VFmt<VF_E4M3>::dec(code) : VFmt<VF_F16>::dec(code), k);
+}
+__device__ __forceinline__ void q_store(bool e4, uint8_t* base, int i, uint32_t code) {
+  if (e4) base[i] = (uint8_t)code;
+  else reinterpret_cast<uint16_t*>(base)[i] = (uint16_t)code;
+}
+__device__ __forceinline__ uint32_t q_load(bool e4, const uint8_t* base, int i) {
+  return e4 ? (uint32_t)base[i] : (uint32_t)reinterpret_cast<const uint16_t*>(base)[i];
+}
+
+constexpr unsigned long long OCC_E4M3 = 1ull << 63;   // bounded format: an E4M3 record
+
+// Bounded E4M3: a kept detail c of a subband with largest kept magnitude m
+// and E4M3 scale 2^k reads back within max(2^-4 |c|, 2^(k-10)) (half a unit
+// of the 3-bit mantissa in the normal range, half the subnormal spacing
+// below it).  The record may use E4M3 when that bound at m is at most half
+// of the subband's threshold thr (exact float32 arithmetic: powers of two).
+__device__ __forceinline__ bool e4m3_bounded(float m, float thr) {
+  const int k = scale_exp<VF_E4M3>(m);
+  const float bound = fmaxf(ldexpf(m, -4), ldexpf(1.0f, k - 10));
+  return bound <= 0.5f * thr;
 }
 
 __device__ __forceinline__ void zero_bytes(uint8_t* p, uint32_t from, uint32_t to) {
@@ -120,7 +140,6 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
   static_assert(sizeof(T) == 4, "narrow formats store float32 coefficients");
   static_assert(sizeof(sm.ghost) >= sizeof(T) * C::M * C::S, "shared-column staging does not fit");
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
-  constexpr int BY = VFmt<VF>::BYTES;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = wave_id();
@@ -226,20 +245,46 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
   // Scales, record layouts and one allocation for the patch (wave 0).
   if (wave == 0) {
     const int nb = L1 * L1;
+    // largest kept magnitude of subband b of field g (0 for the samples)
+    auto band_max = [&sm](int g, int b, int L1_) {
+      const int cyy = b / L1_;
+      const int cxx = b - cyy * L1_;
+      float m = (b == 0) ? 0.0f : sm.nq.smax[g][b];
+      if (C::RIM && cxx == 0 && b != 0) m = fmaxf(m, sm.nq.rmax[g][cyy]);
+      return m;
+    };
+    // bounded format: bit g of f16need when field g's record needs binary16
+    uint32_t f16need = 0u;
+    if constexpr (VF == VF_E4M3B) {
+      const float epsq = (float)patch_eps(a, q);
+      for (int i = lane; i < C::M * nb; i += 64) {
+        const int g = i / nb;
+        const int b = i - g * nb;
+        const float m = band_max(g, b, L1);
+        if (m > 0.0f) {
+          const int cyy = b / L1;
+          const int cxx = b - cyy * L1;
+          const float thr = thr_of<float>(cxx == 0 ? -1 : L - cxx, cyy == 0 ? -1 : L - cyy, epsq, a.rule);
+          if (!e4m3_bounded(m, thr)) f16need |= 1u << g;
+        }
+      }
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) f16need |= (uint32_t)__shfl_xor((int)f16need, d, 64);
+    }
     for (int i = lane; i < C::M * nb; i += 64) {
       const int g = i / nb;
       const int b = i - g * nb;
-      const int cyy = b / L1;
-      const int cxx = b - cyy * L1;
-      float m = (b == 0) ? 0.0f : sm.nq.smax[g][b];
-      if (C::RIM && cxx == 0 && b != 0) m = fmaxf(m, sm.nq.rmax[g][cyy]);
+      const float m = band_max(g, b, L1);
+      const bool e4 = VF == VF_E4M3B ? ((f16need >> g) & 1u) == 0u : fixed_e4<VF>();
       int k = 0;
       if (m > 0.0f) {
-        k = scale_exp<VF>(m);
+        k = e4 ? scale_exp<VF_E4M3>(m) : scale_exp<VF_F16>(m);
         atomicOr(&sm.nq.occ[g], 1ull << b);
       }
       sm.nq.kexp[g][b] = (signed char)k;
     }
+    if (lane < C::M)
+      sm.nq.e4[lane] = (VF == VF_E4M3B ? ((f16need >> lane) & 1u) == 0u : fixed_e4<VF>()) ? 1u : 0u;
     unsigned long long mycol = 0ull;
     if constexpr (C::RIM) {
       const int yy = lane < C::P ? lane : 0;
@@ -259,10 +304,11 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
         sm.corner[lane] = 0u;
       }
       const uint32_t nocc = (uint32_t)__popcll(sm.nq.occ[lane]);
+      const uint32_t by = (VF == VF_E4M3B ? ((f16need >> lane) & 1u) == 0u : fixed_e4<VF>()) ? 1u : 2u;
       const uint32_t ismask = (2u * ndet < 8u * C::W) ? 0u : 1u;
       const uint32_t hb = (8u + 4u * nocc + 7u) & ~7u;
       const uint32_t sb = hb + ((4u * (uint32_t)NS + 7u) & ~7u);
-      const uint32_t vb = sb + ((ndet * (uint32_t)BY + 7u) & ~7u);
+      const uint32_t vb = sb + ((ndet * by + 7u) & ~7u);
       const uint32_t mb = ismask ? 8u * C::W : 2u * ndet;
       rb16 = (vb + mb + 15u) / 16u;
       sm.nnz[lane] = ndet;
@@ -298,6 +344,7 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
     uint8_t* rec = a.pool_out + 16ull * (base16 + sm.rel16[f]);
     float* samp = reinterpret_cast<float*>(rec + sm.nq.hb[f]);
     uint8_t* qv = rec + sm.nq.sb[f];
+    const bool e4 = VF == VF_E4M3B ? sm.nq.e4[f] != 0u : fixed_e4<VF>();
     const bool ismask = sm.ismask[f] != 0u;
     uint16_t* idx = reinterpret_cast<uint16_t*>(rec + sm.vb[f]);
     // samples of the owned lines and of the shared row, exact
@@ -318,9 +365,9 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
           const int rank = run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
           const int k = sm.nq.kexp[f][idx_class(y, L) * L1 + cx];
-          const uint32_t code = q_enc<VF>(v[y], k);
-          q_store<VF>(qv, rank, code);
-          v[y] = q_dec<VF>(code, k);
+          const uint32_t code = q_enc(e4, v[y], k);
+          q_store(e4, qv, rank, code);
+          v[y] = q_dec(e4, code, k);
           if (!ismask) idx[rank] = (uint16_t)(x + C::P * y);
         }
         run += __popcll(b);
@@ -343,16 +390,16 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
           const int rank = run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(col >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)col, 0u));
           const int k = sm.nq.kexp[f][idx_class(yy, L) * L1];
-          q_store<VF>(qv, rank, q_enc<VF>(c, k));
+          q_store(e4, qv, rank, q_enc(e4, c, k));
           if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + yy);
         }
       }
       if ((rowb >> lane) & 1ull) {
         const int rank = run + __popcll(col) + __popcll(rowb & below(x));
         const int k = sm.nq.kexp[f][cx];
-        const uint32_t code = q_enc<VF>(v[C::P], k);
-        q_store<VF>(qv, rank, code);
-        v[C::P] = q_dec<VF>(code, k);
+        const uint32_t code = q_enc(e4, v[C::P], k);
+        q_store(e4, qv, rank, code);
+        v[C::P] = q_dec(e4, code, k);
         if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + C::P + x);
       }
     }
@@ -361,13 +408,14 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
     // the shared column: samples to their slots; details read back as stored
     uint8_t* rec = a.pool_out + 16ull * (base16 + sm.rel16[f]);
     float* samp = reinterpret_cast<float*>(rec + sm.nq.hb[f]);
+    const bool e4 = VF == VF_E4M3B ? sm.nq.e4[f] != 0u : fixed_e4<VF>();
 #pragma unroll
     for (int y = 0; y < C::S; ++y) {
       if ((y & lmask) == 0) {
         samp[(y >> L) * SC + (C::P >> L)] = v[y];
       } else if (v[y] != T(0)) {
         const int k = sm.nq.kexp[f][idx_class(y, L) * L1];
-        v[y] = q_dec<VF>(q_enc<VF>(v[y], k), k);
+        v[y] = q_dec(e4, q_enc(e4, v[y], k), k);
       }
     }
   }
@@ -375,14 +423,15 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
     const int g = tid;
     uint8_t* rec = a.pool_out + 16ull * (base16 + sm.rel16[g]);
     const unsigned long long occ = sm.nq.occ[g];
-    *reinterpret_cast<unsigned long long*>(rec) = occ;
+    const bool e4g = sm.nq.e4[g] != 0u;
+    *reinterpret_cast<unsigned long long*>(rec) = occ | ((VF == VF_E4M3B && e4g) ? OCC_E4M3 : 0ull);
     float* scl = reinterpret_cast<float*>(rec + 8);
     int i = 0;
     for (int b = 1; b < L1 * L1; ++b)
       if ((occ >> b) & 1ull) scl[i++] = ldexpf(1.0f, sm.nq.kexp[g][b]);
     zero_bytes(rec, 8u + 4u * (uint32_t)i, sm.nq.hb[g]);
     zero_bytes(rec, sm.nq.hb[g] + 4u * (uint32_t)NS, sm.nq.sb[g]);
-    zero_bytes(rec, sm.nq.sb[g] + (uint32_t)BY * sm.nnz[g], sm.vb[g]);
+    zero_bytes(rec, sm.nq.sb[g] + (e4g ? 1u : 2u) * sm.nnz[g], sm.vb[g]);
     if constexpr (C::RIM) {
       if (sm.ismask[g]) {
         unsigned long long r[3];
@@ -415,7 +464,6 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
 template <class C, class T, int WAV, bool TOT, int VF, class SM>
 __device__ __forceinline__ void expand_columns_q(const PatchArgs& a, int q, SM& sm) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
-  constexpr int BY = VFmt<VF>::BYTES;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = wave_id();
@@ -434,13 +482,16 @@ __device__ __forceinline__ void expand_columns_q(const PatchArgs& a, int q, SM& 
     const int g = tid;
     const uint32_t ndet = tel(2 * g + 1) & ~MASK_BIT;
     const uint8_t* rec = pool + 16ull * tel(2 * g);
-    const unsigned long long occ = *reinterpret_cast<const unsigned long long*>(rec);
+    const unsigned long long occ0 = *reinterpret_cast<const unsigned long long*>(rec);
+    const bool e4 = VF == VF_E4M3B ? (occ0 & OCC_E4M3) != 0ull : fixed_e4<VF>();
+    const unsigned long long occ = VF == VF_E4M3B ? occ0 & ~OCC_E4M3 : occ0;
     const uint32_t nocc = (uint32_t)__popcll(occ);
     const uint32_t hb = (8u + 4u * nocc + 7u) & ~7u;
     const uint32_t sb = hb + ((4u * (uint32_t)NS + 7u) & ~7u);
     sm.nq.hb[g] = hb;
     sm.nq.sb[g] = sb;
-    sm.vb[g] = sb + ((ndet * (uint32_t)BY + 7u) & ~7u);
+    sm.nq.e4[g] = e4 ? 1u : 0u;
+    sm.vb[g] = sb + ((ndet * (e4 ? 1u : 2u) + 7u) & ~7u);
     const float* scl = reinterpret_cast<const float*>(rec + 8);
     int i = 0;
     for (int b = 1; b < L1 * L1; ++b)
@@ -452,9 +503,11 @@ __device__ __forceinline__ void expand_columns_q(const PatchArgs& a, int q, SM& 
     if (w & MASK_BIT) {
       const uint32_t ndet = w & ~MASK_BIT;
       const uint8_t* rec = pool + 16ull * te(2 * g);
-      const uint32_t nocc = (uint32_t)__popcll(*reinterpret_cast<const unsigned long long*>(rec));
+      const unsigned long long occ0 = *reinterpret_cast<const unsigned long long*>(rec);
+      const bool e4 = VF == VF_E4M3B ? (occ0 & OCC_E4M3) != 0ull : fixed_e4<VF>();
+      const uint32_t nocc = (uint32_t)__popcll(VF == VF_E4M3B ? occ0 & ~OCC_E4M3 : occ0);
       const uint32_t vb = ((8u + 4u * nocc + 7u) & ~7u) + ((4u * (uint32_t)NS + 7u) & ~7u) +
-                          ((ndet * (uint32_t)BY + 7u) & ~7u);
+                          ((ndet * (e4 ? 1u : 2u) + 7u) & ~7u);
       const unsigned long long* words = reinterpret_cast<const unsigned long long*>(rec + vb);
       const int c0 = lane < C::W ? __popcll(words[lane]) : 0;
       const int c1 = (64 + lane) < C::W ? __popcll(words[64 + lane]) : 0;
@@ -501,7 +554,8 @@ __device__ __forceinline__ void expand_columns_q(const PatchArgs& a, int q, SM& 
       }
       record_node<C>(k, xx, yy);
       const int e = sm.nq.kexp[g][idx_class(yy, L) * L1 + idx_class(xx, L)];
-      val = q_dec<VF>(q_load<VF>(rec + sm.nq.sb[g], j), e);
+      const bool e4 = VF == VF_E4M3B ? sm.nq.e4[g] != 0u : fixed_e4<VF>();
+      val = q_dec(e4, q_load(e4, rec + sm.nq.sb[g], j), e);
     }
     sm.tile[C::Lay::fb(g) + yy * C::RS + xx] = val;
   }

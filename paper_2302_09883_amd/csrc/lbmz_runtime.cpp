@@ -30,12 +30,15 @@ bool dispatch_f32_fv_q(LBMZ_DISPATCH_ARGS);
 bool dispatch_f32_lbm_q(LBMZ_DISPATCH_ARGS);
 bool dispatch_f32_euler(LBMZ_DISPATCH_ARGS);
 bool dispatch_f32_d3q19(LBMZ_DISPATCH_ARGS);
+bool dispatch_f32_e4m3b_lbm(LBMZ_DISPATCH_ARGS);
+bool dispatch_f32_e4m3b_fv(LBMZ_DISPATCH_ARGS);
 
 static bool dispatch(LBMZ_DISPATCH_ARGS) {
   return dispatch_f32_fv(k, op, a, grid, s, err, out) || dispatch_f32_lbm(k, op, a, grid, s, err, out) ||
          dispatch_f64_fv(k, op, a, grid, s, err, out) || dispatch_f64_lbm(k, op, a, grid, s, err, out) ||
          dispatch_f32_fv_q(k, op, a, grid, s, err, out) || dispatch_f32_lbm_q(k, op, a, grid, s, err, out) ||
-         dispatch_f32_euler(k, op, a, grid, s, err, out) || dispatch_f32_d3q19(k, op, a, grid, s, err, out);
+         dispatch_f32_euler(k, op, a, grid, s, err, out) || dispatch_f32_d3q19(k, op, a, grid, s, err, out) ||
+         dispatch_f32_e4m3b_lbm(k, op, a, grid, s, err, out) || dispatch_f32_e4m3b_fv(k, op, a, grid, s, err, out);
 }
 
 static size_t dispatch_op_of(const KernelKey& k, int op, const PatchArgs* a, int grid, hipStream_t s,
@@ -181,18 +184,20 @@ int64_t narrow_samples(const lbmz_ctx* c) {
   const int64_t sc = ((c->s - 1) >> c->levels) + 1;
   return sc * sc;
 }
-int64_t narrow_code_bytes(const lbmz_ctx* c) { return c->vf == VF_F16 ? 2 : 1; }
+// Bytes per detail code: 2 (binary16), 1 (E4M3); the bounded format's
+// records use either (bit 63 of OCC), so its worst case is 2.
+int64_t narrow_code_bytes(const lbmz_ctx* c) { return c->vf == VF_E4M3 ? 1 : 2; }
 struct NarrowLayout {
   bool mask;
   int64_t hb, sb, vb, rb;
 };
-NarrowLayout narrow_layout(const lbmz_ctx* c, int64_t ndet, int64_t nocc) {
+NarrowLayout narrow_layout(const lbmz_ctx* c, int64_t ndet, int64_t nocc, int64_t code_bytes) {
   NarrowLayout l;
   const int64_t w = nwords(c);
   l.mask = !(2 * ndet < 8 * w);
   l.hb = align_up(8 + 4 * nocc, 8);
   l.sb = l.hb + align_up(4 * narrow_samples(c), 8);
-  l.vb = l.sb + align_up(ndet * narrow_code_bytes(c), 8);
+  l.vb = l.sb + align_up(ndet * code_bytes, 8);
   l.rb = align_up(l.vb + (l.mask ? 8 * w : 2 * ndet), 16);
   return l;
 }
@@ -200,7 +205,7 @@ NarrowLayout narrow_layout(const lbmz_ctx* c, int64_t ndet, int64_t nocc) {
 int64_t worst_store_bytes(const lbmz_ctx* c) {
   if (c->vf != VF_F32) {
     const int64_t nb = (int64_t)(c->levels + 1) * (c->levels + 1);
-    return narrow_layout(c, ncoef(c), nb - 1).rb * c->nfields * c->npatch;
+    return narrow_layout(c, ncoef(c), nb - 1, narrow_code_bytes(c)).rb * c->nfields * c->npatch;
   }
   return record_bytes(c, ncoef(c), nullptr) * c->nfields * c->npatch;
 }
@@ -583,11 +588,15 @@ int lbmz_create(const lbmz_grid* grid, const lbmz_scheme* scheme, const lbmz_pat
       c->levels = levels;
       c->rule = patch->rule == LBMZ_THR_CAPPED ? R_CAPPED : patch->rule == LBMZ_THR_ACCUM ? R_ACCUM : R_CONSTANT;
       c->eps = eps;
-      if (patch->values != LBMZ_VALUES_F32 && patch->values != LBMZ_VALUES_F16 && patch->values != LBMZ_VALUES_E4M3)
+      if (patch->values != LBMZ_VALUES_F32 && patch->values != LBMZ_VALUES_F16 && patch->values != LBMZ_VALUES_E4M3 &&
+          patch->values != LBMZ_VALUES_E4M3_BOUNDED)
         rc = fail(c, LBMZ_EINVAL, "unknown value format");
       else if (patch->values != LBMZ_VALUES_F32 && c->dtype != 0)
         rc = fail(c, LBMZ_EINVAL, "the narrow value formats need a float32 state");
-      c->vf = patch->values == LBMZ_VALUES_F16 ? VF_F16 : patch->values == LBMZ_VALUES_E4M3 ? VF_E4M3 : VF_F32;
+      c->vf = patch->values == LBMZ_VALUES_F16        ? VF_F16
+              : patch->values == LBMZ_VALUES_E4M3     ? VF_E4M3
+              : patch->values == LBMZ_VALUES_E4M3_BOUNDED ? VF_E4M3B
+                                                      : VF_F32;
       c->key = KernelKey{c->dtype, p, c->wavelet, c->scheme, c->vf};
     }
   }
@@ -1057,9 +1066,14 @@ int lbmz_put_store(lbmz_ctx* c, const uint32_t* table_host, const void* pool_hos
       if (off + 8 > pool_bytes) return fail(c, LBMZ_EINVAL, "record %zu overruns the pool", i);
       uint64_t occ;
       memcpy(&occ, pool + off, 8);
+      int64_t code_bytes = narrow_code_bytes(c);
+      if (c->vf == VF_E4M3B) {   // bit 63: an E4M3 record, else binary16
+        code_bytes = (occ >> 63) ? 1 : 2;
+        occ &= ~(1ull << 63);
+      }
       if ((occ & 1ull) || (nbands < 64 && (occ >> nbands) != 0))
         return fail(c, LBMZ_EINVAL, "record %zu: bad subband mask", i);
-      const NarrowLayout l = narrow_layout(c, nnz, __builtin_popcountll(occ));
+      const NarrowLayout l = narrow_layout(c, nnz, __builtin_popcountll(occ), code_bytes);
       mask = l.mask;
       rb = l.rb;
       vb = l.vb;

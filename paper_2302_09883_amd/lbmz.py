@@ -22,7 +22,7 @@ SCHEMES = {"fv_upwind": 0, "d2q9_bgk": 1, "euler_rusanov": 2, "d3q19_bgk": 3}
 WAVELETS = {"haar": 0, "bl53": 1}
 RULES = {"capped": 0, "constant": 1, "accum": 2}
 DTYPES = {"f32": 0, "f64": 1}
-VALUES = {"f32": 0, "f16": 1, "e4m3": 2}
+VALUES = {"f32": 0, "f16": 1, "e4m3": 2, "e4m3b": 3}
 NP_DTYPES = {"f32": np.float32, "f64": np.float64}
 MASK_BIT = 1 << 31
 

@@ -38,7 +38,7 @@ STEPS = 500
 GAMMA = 1.4
 CFL = 0.4
 SEED = 0
-FORMATS = ("f32", "f16", "e4m3")
+FORMATS = ("f32", "f16", "e4m3", "e4m3b")
 
 
 def problem(n: int = N, seed: int = SEED):

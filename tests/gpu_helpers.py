@@ -80,7 +80,6 @@ def _decode_narrow(table, pool, s, values, levels):
     ns = sc * sc
     cls = np.array([0 if i % step == 0 else (i & -i).bit_length() for i in range(s)])
     band = (cls[:, None] * (levels + 1) + cls[None, :]).reshape(-1)[order]
-    by = 2 if values == "f16" else 1
     buf = np.frombuffer(pool, dtype=np.uint8)
     out = np.zeros((npatch, nf, s, s), dtype=np.float32)
     for q in range(npatch):
@@ -89,6 +88,11 @@ def _decode_narrow(table, pool, s, values, levels):
             word = int(table[q, f, 1])
             ndet = word & (O.MASK_BIT - 1)
             occ = int(buf[off:off + 8].view("<u8")[0])
+            fmt = values
+            if values == "e4m3b":   # bit 63: an E4M3 record, else binary16
+                fmt = "e4m3" if (occ >> 63) & 1 else "f16"
+                occ &= (1 << 63) - 1
+            by = 2 if fmt == "f16" else 1
             bands = [b for b in range(64) if (occ >> b) & 1]
             scale = dict(zip(bands, buf[off + 8:off + 8 + 4 * len(bands)].view("<f4")))
             hb = (8 + 4 * len(bands) + 7) // 8 * 8
@@ -99,7 +103,7 @@ def _decode_narrow(table, pool, s, values, levels):
             if ndet == 0:
                 continue
             raw = buf[off + sb:off + sb + by * ndet]
-            vals = raw.view("<f2").astype(np.float32) if values == "f16" else _e4m3_values(raw)
+            vals = raw.view("<f2").astype(np.float32) if fmt == "f16" else _e4m3_values(raw)
             if word & O.MASK_BIT:
                 bits = np.unpackbits(buf[off + vb:off + vb + 8 * w], bitorder="little")[:nc].astype(bool)
                 ks = np.flatnonzero(bits)

@@ -161,3 +161,73 @@ def test_e4m3_on_strong_shocks_stops_cleanly_or_runs():
         assert 0 <= st["steps"] < 50
         f = ctx.fields()
         assert np.all(np.isfinite(f))
+
+
+def test_bounded_e4m3_runs_the_strong_shocks():
+    """The bounded E4M3 format keeps E4M3 codes only where their rounding
+    stays within half of each subband's threshold: the shock records go to
+    binary16, and the run that plain E4M3 cannot finish completes."""
+    _say("euler e4m3b strong")
+    rel = _run_totals("e4m3b", seed=2)
+    assert rel <= 2e-3
+
+
+def test_bounded_e4m3_full_precision_workload():
+    """The precision workload at its size and length: 4096^2, 64^2 patches,
+    BL5/3 L = 5, eps = 1e-4, four-quadrant shocks, 500 steps, bounded E4M3
+    records: no non-finite stop, every conserved total kept to float32
+    round-off, positive density."""
+    n, p, levels, eps, steps = 4096, 64, 5, 1e-4, 500
+    _say("euler e4m3b 4096^2 x 500")
+    w, states = riemann_four_quadrants(n, seed=0, gamma=G)
+    smax = 2.0 * max(np.sqrt(G * pp / r) for r, pp in states)
+    ctx = _ctx(n, p, "bl53", levels, eps, smax, values="e4m3b")
+    _set(ctx, w)
+    t0 = np.array(ctx.stats()["totals"])
+    ctx.step(steps)
+    st = ctx.stats()
+    t1 = np.array(st["totals"])
+    ref = np.abs(w).sum(axis=(1, 2))
+    assert st["steps"] == steps
+    assert np.all(np.abs(t1 - t0) <= 2e-6 * ref + 1e-2), (t0, t1)
+    rho = ctx.decompress_field(0)
+    assert np.all(np.isfinite(rho)) and float(rho.min()) > 0
+    print(f"[case] euler e4m3b 4096^2: ratio {st['ratio']:.1f}, mask/list records "
+          f"{st['mask_records']}/{st['list_records']}", flush=True)
+
+
+def test_errors_against_the_fp64_oracle():
+    """Every storage format's error against the float64 oracle, on a grid the
+    oracle steps in seconds: the precision workload's geometry (64^2 patches,
+    BL5/3 L = 5, capped eps = 1e-4, four-quadrant shocks) on 256^2 for 100
+    steps.  References: the oracle's uncompressed scheme and its compressed
+    patch loop, both in float64.  The float32-record GPU run must track the
+    float64 compressed run (its error against the plain scheme within 10 %);
+    binary16 details add at most 10 % to that error, bounded E4M3 at most
+    50 % (its codes are off by at most half a threshold)."""
+    n, p, levels, eps, steps = 256, 64, 5, 1e-4, 100
+    _say("euler errors vs fp64 oracle")
+    w, smax = _problem(n, seed=0)
+    sch = O.Scheme("euler_rusanov", vel=(smax, 0.0), cfl=CFL, gamma=G)
+    plain = w.copy()
+    for _ in range(steps):
+        plain = O.dense_step(plain, sch)
+    run64 = O.CompressedRun(O.Geometry(n, p, O.BL53, levels), sch, eps, O.RULE_CAPPED, np.float64)
+    run64.set_grid(w)
+    run64.step(steps)
+    e64 = O.l2_errors(run64.grid(), plain, 1.0 / n ** 2)[2]
+    errs = {}
+    for values in ("f32", "f16", "e4m3b"):
+        ctx = _ctx(n, p, "bl53", levels, eps, smax, values=values)
+        _set(ctx, w)
+        ctx.step(steps)
+        got = ctx.fields().astype(np.float64)
+        _, _, rel_plain, linf_plain = O.l2_errors(got, plain, 1.0 / n ** 2)
+        rel_c64 = O.l2_errors(got, run64.grid(), 1.0 / n ** 2)[2]
+        errs[values] = rel_plain
+        print(f"[case] euler {values}: rel L2 vs fp64 plain {rel_plain:.3e} (Linf {linf_plain:.3e}), "
+              f"vs fp64 compressed {rel_c64:.3e}; fp64 compressed vs plain {e64:.3e}; "
+              f"ratio {ctx.stats()['ratio']:.1f}", flush=True)
+    assert abs(errs["f32"] - e64) <= 0.1 * e64
+    assert errs["f16"] <= 1.1 * errs["f32"]
+    assert errs["e4m3b"] <= 1.5 * errs["f32"]

@@ -46,6 +46,9 @@ def _record(table, pool, q, f, g, levels, fmt):
     word = int(table[q, f, 1])
     ndet = word & (O.MASK_BIT - 1)
     occ = int(np.frombuffer(pool, dtype="<u8", count=1, offset=off)[0])
+    if fmt == "e4m3b":
+        fmt = "e4m3" if occ & Q.OCC_E4M3_BIT else "f16"
+        occ &= ~Q.OCC_E4M3_BIT
     nsamp = len(Q.sample_positions(g.s, levels)[0])
     rb = Q.record_layout_q(ndet, bin(occ).count("1"), g.s * g.s, nsamp, fmt)[4]
     return pool[off:off + rb]
@@ -90,7 +93,7 @@ def test_narrow_compaction_byte_exact(fmt, geom, eps, zero_frac):
     table, pool = ctx.store()
     for q in range(g.npatch):
         for f in range(ctx.nfields):
-            rec, ndet, is_mask = Q.encode_record_q(kept[q, f], levels, fmt)
+            rec, ndet, is_mask = Q.encode_record_q(kept[q, f], levels, fmt, twin.thr)
             assert int(table[q, f, 1]) == ndet | (O.MASK_BIT if is_mask else 0), (q, f)
             assert _record(table, pool, q, f, g, levels, fmt) == rec, (q, f)
     spans = sorted((int(table[q, f, 0]) * 16, len(_record(table, pool, q, f, g, levels, fmt)))
@@ -183,7 +186,42 @@ def test_narrow_run_conserves_and_shrinks(fmt):
     a, b = runs["f32"][1], runs[fmt][1]
     rel = np.linalg.norm(a - b) / np.linalg.norm(a)
     print("[case] narrow run rel_l2 vs float32 records", fmt, rel, "store bytes", runs[fmt][0], runs["f32"][0])
-    assert rel <= (1e-4 if fmt == "f16" else 2e-2), rel
+    # (eps = 0: the bounded format stores every record with a detail in binary16)
+    assert rel <= (1e-4 if fmt in ("f16", "e4m3b") else 2e-2), rel
+
+
+@pytest.mark.parametrize("geom", [GEOMS[0], GEOMS[3]])
+def test_bounded_e4m3_records_of_both_kinds_byte_exact(geom):
+    """Records whose kept details stay within 8x their subband threshold are
+    E4M3 (the rounding bound is then at most half the threshold), the others
+    binary16; every record byte-identical to the oracle's."""
+    n, scheme, p, wavelet, levels = geom
+    eps = 1e-3
+    _say("bounded e4m3 records", geom)
+    ctx = make_ctx(n, scheme, "f32", p, wavelet, levels, eps, values="e4m3b")
+    twin = _twin(n, scheme, p, wavelet, levels, eps, "e4m3b")
+    g = twin.g
+    rng = np.random.default_rng(41)
+    sb = Q.subband_table(g.s, levels)
+    tiles = np.zeros((g.npatch, ctx.nfields, g.s, g.s), dtype=np.float32)
+    for q in range(g.npatch):
+        for f in range(ctx.nfields):
+            top = 6.0 if (q + f) % 2 == 0 else 40.0
+            t = twin.thr * rng.uniform(1.0, top, (g.s, g.s)) * rng.choice([-1.0, 1.0], (g.s, g.s))
+            t[rng.random((g.s, g.s)) < 0.7] = 0
+            t[sb == 0] = rng.uniform(0.5, 1.5, int((sb == 0).sum()))
+            tiles[q, f] = t
+    ctx.set_coefficients(tiles)
+    kept = O.hard_threshold(tiles, twin.thr)
+    table, pool = ctx.store()
+    kinds = {"e4m3": 0, "f16": 0}
+    for q in range(g.npatch):
+        for f in range(ctx.nfields):
+            rec, ndet, is_mask = Q.encode_record_q(kept[q, f], levels, "e4m3b", twin.thr)
+            assert int(table[q, f, 1]) == ndet | (O.MASK_BIT if is_mask else 0), (q, f)
+            assert _record(table, pool, q, f, g, levels, "e4m3b") == rec, (q, f)
+            kinds[Q.effective_format(kept[q, f], levels, "e4m3b", twin.thr)] += 1
+    assert kinds["e4m3"] > 0 and kinds["f16"] > 0, kinds
 
 
 def test_narrow_formats_need_float32():

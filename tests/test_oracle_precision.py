@@ -76,7 +76,10 @@ def test_f16_matches_the_struct_half_float_packing():
 
 # ---------------------------------------------------------------- scales
 
-@pytest.mark.parametrize("fmt", Q.FORMATS)
+FIXED = ("f16", "e4m3")
+
+
+@pytest.mark.parametrize("fmt", FIXED)
 def test_pow2_scale_is_the_tightest_power_of_two(fmt):
     rng = np.random.default_rng(9)
     for m in np.concatenate([rng.uniform(1e-9, 1e6, 500), [448.0, 65504.0, 1.0, 2.0 ** -30]]):
@@ -94,15 +97,26 @@ def _tile(s, L, seed, zero_frac):
     return t
 
 
+def _thr(s, L, eps=1e-3, rule="capped"):
+    return O.threshold_table(s, L, eps, rule, np.float32)
+
+
 @pytest.mark.parametrize("fmt", Q.FORMATS)
 @pytest.mark.parametrize("s,L", [(65, 5), (65, 2), (33, 4), (64, 6), (16, 3)])
 @pytest.mark.parametrize("zero_frac", [0.0, 0.9, 0.995, 1.0])
 def test_record_roundtrip_and_layout(fmt, s, L, zero_frac):
     t = _tile(s, L, seed=s + L, zero_frac=zero_frac)
-    buf, ndet, is_mask = Q.encode_record_q(t, L, fmt)
+    thr = _thr(s, L) if fmt == "e4m3b" else None
+    buf, ndet, is_mask = Q.encode_record_q(t, L, fmt, thr)
     back = Q.decode_record_q(buf, 0, ndet | (O.MASK_BIT if is_mask else 0), s, L, fmt)
-    deq, scales, occ = Q.quantize_tile(t, L, fmt)
+    deq, scales, occ = Q.quantize_tile(t, L, fmt, thr)
     assert np.array_equal(back.view(np.uint32), deq.view(np.uint32))
+    eff = Q.effective_format(t, L, fmt, thr)
+    if fmt == "e4m3b":
+        assert bool(occ & Q.OCC_E4M3_BIT) == (eff == "e4m3")
+        occ &= ~Q.OCC_E4M3_BIT
+        # the e4m3b record reads back as the record of its effective format
+        assert np.array_equal(deq.view(np.uint32), Q.quantize_tile(t, L, eff)[0].view(np.uint32))
     # brute force: kept details in record order, samples untouched, sizes
     sb = Q.subband_table(s, L)
     order = O.record_order(s)
@@ -113,14 +127,14 @@ def test_record_roundtrip_and_layout(fmt, s, L, zero_frac):
     assert occ == sum(1 << b for b in set(sb[(sb != 0) & (t != 0)].tolist()))
     assert len(buf) % 16 == 0
     nsamp = len(Q.sample_positions(s, L)[0])
-    assert len(buf) == Q.record_layout_q(ndet, len(scales), s * s, nsamp, fmt)[4]
+    assert len(buf) == Q.record_layout_q(ndet, len(scales), s * s, nsamp, eff)[4]
     if not is_mask and ndet:
-        *_, vb, _ = Q.record_layout_q(ndet, len(scales), s * s, nsamp, fmt)
+        *_, vb, _ = Q.record_layout_q(ndet, len(scales), s * s, nsamp, eff)
         idx = np.frombuffer(buf, dtype="<u2", count=ndet, offset=vb)
         assert idx.tolist() == [k for k, _ in det]
 
 
-@pytest.mark.parametrize("fmt", Q.FORMATS)
+@pytest.mark.parametrize("fmt", FIXED)
 def test_quantisation_error_bounds(fmt):
     t = _tile(65, 5, seed=3, zero_frac=0.2)
     deq, scales, _ = Q.quantize_tile(t, 5, fmt)
@@ -143,7 +157,8 @@ def test_mass_unchanged_by_quantisation(fmt):
     rng = np.random.default_rng(4)
     tile = rng.uniform(0.5, 1.5, (65, 65))
     coef = O.forward_2d(tile, 5, O.BL53).astype(np.float32)
-    deq, _, _ = Q.quantize_tile(coef, 5, fmt)
+    # e4m3b: a threshold table of zeros (eps = 0) makes the record binary16
+    deq, _, _ = Q.quantize_tile(coef, 5, fmt, _thr(65, 5, 0.0) if fmt == "e4m3b" else None)
     assert not np.array_equal(deq, coef)
     w = np.ones(65)
     w[0] = w[-1] = 0.5
@@ -157,8 +172,73 @@ def test_store_roundtrip():
     rng = np.random.default_rng(5)
     coef = rng.standard_normal((3, 2, 33, 33)).astype(np.float32)
     coef[rng.random(coef.shape) < 0.97] = 0
+    thr = _thr(33, 4, 0.3)
     for fmt in Q.FORMATS:
-        table, pool = Q.encode_store_q(coef, 4, fmt)
+        th = thr if fmt == "e4m3b" else None
+        table, pool = Q.encode_store_q(coef, 4, fmt, th)
         back = Q.decode_store_q(table, pool, 33, 4, fmt)
-        assert np.array_equal(back, Q.quantize_tiles(coef, 4, fmt))
-        assert Q.store_bytes_q(coef, 4, fmt) == len(pool) + table.size * 4
+        assert np.array_equal(back, Q.quantize_tiles(coef, 4, fmt, th))
+        assert Q.store_bytes_q(coef, 4, fmt, th) == len(pool) + table.size * 4
+
+
+# ---------------------------------------------------------------- e4m3b choice
+
+def _bounded_tiles(seed, n=40):
+    """Thresholded tiles whose kept details span [thr, 30 thr] per subband."""
+    rng = np.random.default_rng(seed)
+    s, L = 33, 4
+    thr = _thr(s, L, 1e-3)
+    tiles = []
+    for _ in range(n):
+        top = rng.choice([2.0, 6.0, 7.9, 12.0, 30.0])
+        t = (thr * rng.uniform(1.0, top, (s, s)) * rng.choice([-1.0, 1.0], (s, s))).astype(np.float32)
+        t[rng.random((s, s)) < rng.uniform(0.3, 0.98)] = 0
+        samples = Q.subband_table(s, L) == 0
+        t[samples] = rng.uniform(0.5, 1.5, int(samples.sum())).astype(np.float32)
+        tiles.append(t)
+    return tiles, thr, L
+
+
+def test_e4m3b_records_keep_the_quantisation_within_half_the_threshold():
+    # brute force over every kept detail of every record that the rule stores
+    # in E4M3: its read-back error is at most half its threshold
+    tiles, thr, L = _bounded_tiles(21)
+    sb = Q.subband_table(33, L)
+    chosen = {"e4m3": 0, "f16": 0}
+    for t in tiles:
+        eff = Q.effective_format(t, L, "e4m3b", thr)
+        chosen[eff] += 1
+        deq = Q.quantize_tile(t, L, "e4m3b", thr)[0]
+        if eff == "e4m3":
+            det = (sb != 0) & (t != 0)
+            err = np.abs(deq[det].astype(np.float64) - t[det].astype(np.float64))
+            assert np.all(err <= 0.5 * thr[det].astype(np.float64))
+    assert chosen["e4m3"] > 0 and chosen["f16"] > 0
+
+
+def test_e4m3b_choice_at_the_edge_of_the_bound():
+    # one kept detail in the finest subband of a capped L = 4 tile: E4M3 up to
+    # 8 thr (2^-4 * 8 thr = thr / 2), binary16 just above
+    s, L = 33, 4
+    thr = _thr(s, L, 1e-3)
+    t = np.zeros((s, s), dtype=np.float32)
+    t[0, 0] = 1.0
+    y, x = 1, 1                              # finest level in both dimensions
+    for mult, want in ((1.0, "e4m3"), (8.0, "e4m3"), (float(np.nextafter(np.float32(8.0), np.float32(9.0))), "f16"),
+                       (100.0, "f16")):
+        t[y, x] = np.float32(thr[y, x] * np.float32(mult))
+        assert Q.effective_format(t, L, "e4m3b", thr) == want, mult
+    # eps = 0: zero thresholds, any kept detail needs binary16; no detail at all: E4M3
+    t[y, x] = 1e-3
+    assert Q.effective_format(t, L, "e4m3b", _thr(s, L, 0.0)) == "f16"
+    t[y, x] = 0.0
+    assert Q.effective_format(t, L, "e4m3b", _thr(s, L, 0.0)) == "e4m3"
+
+
+def test_e4m3b_store_lies_between_the_fixed_formats():
+    tiles, thr, L = _bounded_tiles(22, n=24)
+    coef = np.stack(tiles).reshape(6, 4, 33, 33)
+    b8 = Q.store_bytes_q(coef, L, "e4m3", thr)
+    b16 = Q.store_bytes_q(coef, L, "f16", thr)
+    bb = Q.store_bytes_q(coef, L, "e4m3b", thr)
+    assert b8 < bb < b16

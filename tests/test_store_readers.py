@@ -38,11 +38,19 @@ def test_reader_matches_oracle_encoder(s, dtype):
     assert np.array_equal(got, O.decode_store(table, pool, s, dtype))
 
 
-@pytest.mark.parametrize("fmt", ["f16", "e4m3"])
+@pytest.mark.parametrize("fmt", ["f16", "e4m3", "e4m3b"])
 def test_narrow_reader_matches_oracle_encoder(fmt):
     levels = 5
     tiles = _mixed_tiles((2, 3, 65, 65), seed=7, dtype=np.float32) * np.float32(1e-2)
-    table, pool = Q.encode_store_q(tiles, levels, fmt)
+    thr = None
+    if fmt == "e4m3b":
+        # per-tile thresholds: every other tile gets a large one, so both record formats occur
+        thr = np.stack([O.threshold_table(65, levels, e, "capped", np.float32)
+                        for e in (1e-9, 1.0)] * 3).reshape(2, 3, 65, 65)
+    table, pool = Q.encode_store_q(tiles, levels, fmt, thr)
+    if fmt == "e4m3b":
+        occ = [int(np.frombuffer(pool, dtype="<u8", count=1, offset=16 * int(o))[0]) for o in table[..., 0].ravel()]
+        assert any(o >> 63 for o in occ) and any(not o >> 63 for o in occ)
     got = gh.decode_records(table, pool, 65, np.float32, values=fmt, levels=levels)
     want = Q.decode_store_q(table, pool, 65, levels, fmt)
     assert np.array_equal(got, want)
