@@ -658,27 +658,40 @@ __device__ __forceinline__ void collide_node(float* fi, float om) {
   }
 }
 
+// Buffer resource over the workgroup's scratch slice (19 fields of SF
+// floats): loads and stores address it by a per-thread byte offset and a
+// per-population offset held in a scalar register, so that the 19 streams of
+// the collision need no per-population 64-bit address in vector registers.
+// Accesses outside the slice read 0 and write nothing.
+template <class C>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t scratch_rsrc(float* scr) {
+  return __builtin_amdgcn_make_buffer_rsrc(scr, 0, (int)(sizeof(float) * C::M * C::SF), 0x00020000);
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <class C>
 __device__ void collide(const PatchArgs& a, float* scr) {
   const float om = (float)a.omega;
-  // two consecutive nodes per thread and iteration: 19 8-byte loads in flight
-  for (int i2 = threadIdx.x; i2 < C::SF / 2; i2 += C::NT) {
-    float2 q[19];
+  const __amdgpu_buffer_rsrc_t rs = scratch_rsrc<C>(scr);
+  constexpr int FB = (int)sizeof(float) * C::SF;   // bytes per population
+  // Four consecutive nodes per thread and iteration: 19 16-byte loads in
+  // flight per lane, then the four collisions, then 19 16-byte stores.
+  for (int i4 = threadIdx.x; i4 < C::SF / 4; i4 += C::NT) {
+    u32x4 q[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) q[i] = reinterpret_cast<const float2*>(scr + (size_t)i * C::SF)[i2];
-    float f[19];
+    for (int k = 0; k < 19; ++k) q[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * i4, k * FB, 0);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) f[i] = q[i].x;
-    collide_node<C>(f, om);
+    for (int e = 0; e < 4; ++e) {
+      float f[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) q[i].x = f[i];
+      for (int k = 0; k < 19; ++k) f[k] = __uint_as_float(q[k][e]);
+      collide_node<C>(f, om);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) f[i] = q[i].y;
-    collide_node<C>(f, om);
+      for (int k = 0; k < 19; ++k) q[k][e] = __float_as_uint(f[k]);
+    }
 #pragma unroll
-    for (int i = 0; i < 19; ++i) q[i].y = f[i];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) reinterpret_cast<float2*>(scr + (size_t)i * C::SF)[i2] = q[i];
+    for (int k = 0; k < 19; ++k) __builtin_amdgcn_raw_buffer_store_b128(q[k], rs, 16 * i4, k * FB, 0);
   }
 }
 
