@@ -469,6 +469,12 @@ def main():
     roof["flops_per_lup"] = round(flops_launch / (N * N), 1)
     roof["bytes_per_launch"] = round(prim["bytes_per_launch"])
 
+    shape = None
+    if not args.no_autotune:
+        from paper_2302_09883_amd.execution import tune_patch_shape
+        shape = tune_patch_shape(N, PRIMARY_EPS)
+        print(f"[bench] patch-shape tuner: {shape['chosen']}", file=sys.stderr, flush=True)
+
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -497,7 +503,7 @@ def main():
         "config": {"workload": "D2Q9 BGK tau=0.6, 2048x2048 periodic, 64x64 patches, folded BL5/3 L=5, "
                                "capped threshold, double shear layer",
                    "grid": N, "patch": P, "levels": LEVELS, "eps": PRIMARY_EPS, "parallelism": "single GPU",
-                   "execution": prim["execution"]},
+                   "execution": dict(prim["execution"], patch_shape=shape)},
         "compression_ratio": round(prim["ratio"], 2),
         "rel_l2_vs_uncompressed": prim["rel_l2"],
         "error_steps": total,

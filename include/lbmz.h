@@ -301,9 +301,26 @@ int lbmz_autotune(lbmz_ctx* ctx, int steps_per_variant, float* ms_out);
  * q (patch index px + (n/p) py) in every following step and set-up call;
  * count = npatch (host values must be finite and >= 0; device values are the
  * caller's responsibility), or count = 0 to return to the single eps.  The
- * threshold rule and levels stay those of the context (Section 2.2 gives one
- * constant per run; a constant per patch is the learned part's control). */
+ * threshold rule stays that of the context (Section 2.2 gives one constant
+ * per run; a constant per patch is the learned part's control); shared
+ * bordering lines take the smaller threshold of their tiles (see
+ * lbmz_set_patch_levels).  2-D contexts with float32 records only. */
 int lbmz_set_patch_eps(lbmz_ctx* ctx, const double* eps, size_t count, int on_device);
+
+/* Per-patch threshold level counts: levels[q] (0 <= levels[q] <= L) takes
+ * the place of L in the thresholds of patch q (patch index px + (n/p) py) in
+ * every following step and set-up call: the levels[q] finest detail levels
+ * may be zeroed, with ranks counted from the coarsest of them, and the
+ * coefficients of coarser levels are kept like samples (levels[q] = 0 keeps
+ * every coefficient).  The transform keeps its L levels.  count = npatch, or
+ * count = 0 to return to L.  Section 2.2 gives one threshold and one level
+ * count per run; per patch they are the learned part's controls.  With
+ * per-patch thresholds or level counts, a bordering line of BL5/3 tiles
+ * (stored by both tiles that share it, Section 3.1.1) takes, entry by entry,
+ * the smaller threshold of the two tiles, so that both keep the same
+ * coefficients of it and the shared values, and the conservation of the
+ * totals, hold.  2-D contexts with float32 records only (LBMZ_EINVAL). */
+int lbmz_set_patch_levels(lbmz_ctx* ctx, const int* levels, size_t count);
 
 /* With on != 0, every step also writes each patch's network input: the
  * stored coefficients of every field at the owned positions (8 i, 8 j),
@@ -312,24 +329,35 @@ int lbmz_set_patch_eps(lbmz_ctx* ctx, const double* eps, size_t count, int on_de
 int lbmz_enable_features(lbmz_ctx* ctx, int on);
 
 /* Copy the inputs written by the last completed lbmz_step; LBMZ_ESTATE when
- * they are not enabled or no step has completed since. */
+ * they are not enabled or no step has completed since.  Layout, float32
+ * [npatch][4 nfields][8][8]: channel f < nfields holds field f's stored
+ * coefficients at the owned positions (8 i, 8 j) (index j * 8 + i);
+ * channel nfields + 3 f + l - 1 the energy (sum of squares, before the
+ * threshold) of field f's coefficients of level l = 1, 2, 3 in the 8 x 8
+ * block of owned positions [8 i, 8 i + 8) x [8 j, 8 j + 8) (a coefficient's
+ * level is the finer of its two per-dimension levels, Section 2.2's classes;
+ * every coefficient of a block but its stride-8 corner has a level <= 3).
+ * 2-D float32 records and 64 x 64 patches only. */
 int lbmz_get_features(lbmz_ctx* ctx, float* dst, size_t bytes, int dst_on_device);
 
 /* ---- the learned threshold predictor ---------------------------------------
  * A small convolutional network (bfloat16 weights, float32 accumulation) that
- * maps a patch's network input (lbmz_get_features) to K predicted log10
- * squared errors, one per candidate threshold:
- *   asinh(x / 1e-4) [9][8][8] -> conv 3x3 9->32, ReLU -> conv 3x3 32->32, ReLU
+ * maps a patch's features (lbmz_get_features, 36 channels for the 9 D2Q9
+ * populations) to K outputs (the caller's targets, e.g. predicted log10
+ * window errors and record bytes of K candidate controls):
+ *   input map [12][8][8]: asinh(c / 1e-4) of the 9 coefficient channels and
+ *   asinh(sqrt(sum over fields of the level-l energy) / 1e-4), l = 1, 2, 3
+ *   -> conv 3x3 12->32, ReLU -> conv 3x3 32->32, ReLU
  *   -> conv 3x3 stride 2 32->32, ReLU -> mean over 4 x 4 -> linear 32->K.
- * Parameters, float32, in this order: w1[32][9][3][3], b1[32],
+ * Parameters, float32, in this order: w1[32][12][3][3], b1[32],
  * w2[32][32][3][3], b2[32], w3[32][32][3][3], b3[32], wh[K][32], bh[K]
- * (21120 + 33 K values).  The float32 master copy is what set/get exchange;
+ * (21984 + 33 K values).  The float32 master copy is what set/get exchange;
  * every pass uses its round-to-nearest-even bfloat16 copy.  Loss of a batch:
  * the mean of its B x K squared differences to the targets; training is Adam
- * (beta1 0.9, beta2 0.999, eps 1e-8) on the master copy.  x: [B][9][8][8],
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on the master copy.  x: [B][36][8][8],
  * targets and outputs: [B][K], float32, host or device (on_device). */
 typedef struct lbmz_net lbmz_net;
-int lbmz_net_create(int k, lbmz_net** out);          /* 1 <= k <= 16; parameters start at 0 */
+int lbmz_net_create(int k, lbmz_net** out);          /* 1 <= k <= 32; parameters start at 0 */
 int lbmz_net_param_count(const lbmz_net* net);
 int lbmz_net_set_stream(lbmz_net* net, void* hip_stream);
 int lbmz_net_set_params(lbmz_net* net, const float* params, size_t count);   /* host; resets Adam */
@@ -350,11 +378,11 @@ int lbmz_net_train_step(lbmz_net* net, const float* x, const float* t, int batch
  * and grows with the batch) live in one fixed device array of
  * LBMZ_NET_SCRATCH_BYTES per GPU, set up by lbmz_net_create and held until
  * the process ends; this call allocates nothing and frees nothing.
- * x [batch][9][8][8], t [batch][K], grad [param_count] and loss [1] are
+ * x [batch][36][8][8], t [batch][K], grad [param_count] and loss [1] are
  * float32 device pointers on the network's device; grad and *loss are
  * written.  The call is asynchronous on the network's stream.  The workspace
  * needs ceil(batch / 16) * (4 * param_count) bytes, rounded up to 256, plus
- * 4 * ceil(batch / 16): a batch above that (3104 samples at K = 12) returns
+ * 4 * ceil(batch / 16): a batch above that (2992 samples at K = 12) returns
  * LBMZ_EINVAL with the limit in lbmz_net_last_error.  Every call on one GPU
  * shares its array (each call fully rewrites the part it reads), so calls
  * that overlap in time on one GPU -- from any network or stream -- race. */

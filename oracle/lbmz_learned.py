@@ -13,18 +13,23 @@ coefficients, the error each candidate would cause.
 Network (plain definition, float64 here; the GPU stores the weights in
 bfloat16 and accumulates in float32):
 
-  input  x[B, 9, 8, 8]    coarse view of a patch: every field's coefficients
-                          at the 8 x 8 owned positions of stride 8, mapped by
-                          asinh(c / 1e-4)
-  conv1  3x3, pad 1, 9 -> 32 channels, bias, ReLU
+  input  raw[B, 36, 8, 8] the patch features: channels 0..8 every field's
+                          coefficients at the 8 x 8 owned positions of stride
+                          8; channel 9 + 3 f + l - 1 the energy (sum of
+                          squares) of field f's coefficients of level l
+                          (l = 1, 2, 3, the finer of the two per-dimension
+                          levels) in each 8 x 8 block of owned positions
+  map    x[B, 12, 8, 8]   asinh(c / 1e-4) of the 9 coefficient channels, and
+                          asinh(sqrt(sum over fields of the level-l energy) / 1e-4)
+  conv1  3x3, pad 1, 12 -> 32 channels, bias, ReLU
   conv2  3x3, pad 1, 32 -> 32, bias, ReLU
   conv3  3x3, pad 1, stride 2, 32 -> 32 (output 4 x 4), bias, ReLU
   pool   mean over the 4 x 4 positions -> [B, 32]
   head   linear 32 -> K, bias: predicted log10 of the patch's squared error
          for each of the K candidate thresholds
 
-Loss: mean squared difference to the measured log10 errors.  Parameters:
-2,624 + 9,248 + 9,248 + 33 K (21,318 for K = 6).
+Loss: mean squared difference to the targets.  Parameters:
+3,488 + 9,248 + 9,248 + 33 K (22,380 for K = 12).
 
 Gradients are written out by hand (the chain rule through each layer) and
 pinned in the tests against central finite differences of the loss.
@@ -33,7 +38,9 @@ from __future__ import annotations
 
 import numpy as np
 
-C_IN = 9
+C_FIELDS = 9
+C_RAW = 4 * C_FIELDS
+C_IN = C_FIELDS + 3
 C_HID = 32
 SIDE = 8
 FEATURE_SCALE = 1e-4
@@ -144,10 +151,49 @@ def adam_step(p: dict, m: dict, v: dict, grads: dict, step: int, lr: float = 1e-
         p[name] = p[name] - lr * mh / (np.sqrt(vh) + eps)
 
 
-def features(coef: np.ndarray) -> np.ndarray:
-    """Network input of coefficient tiles ``[B, 9, s, s]``: stride-8 owned positions, asinh-scaled."""
-    sub = coef[:, :, 0:SIDE * 8:8, 0:SIDE * 8:8].astype(np.float64)
-    return np.arcsinh(sub / FEATURE_SCALE)
+def coefficient_levels(s: int, levels: int) -> np.ndarray:
+    """Level of each coefficient of an ``s x s`` tile: the finer of its two
+    per-dimension levels (1 = finest); a sample index counts as coarser than
+    any level, so pure samples get a level above ``levels``."""
+    lev = np.full(s, levels + 1, dtype=np.int64)
+    for i in range(s):
+        if i % (1 << levels):
+            lev[i] = 1 + (i & -i).bit_length() - 1
+    return np.minimum(lev[:, None], lev[None, :])
+
+
+def raw_features(coef: np.ndarray, levels: int) -> np.ndarray:
+    """The patch features of coefficient tiles ``[B, 9, s, s]`` (64 x 64
+    patches): the stride-8 coefficients and, per field, the energy of the
+    level 1, 2 and 3 coefficients of every 8 x 8 block, ``[B, 36, 8, 8]``."""
+    c = np.asarray(coef, dtype=np.float64)
+    b, m = c.shape[0], c.shape[1]
+    out = np.zeros((b, 4 * m, SIDE, SIDE))
+    out[:, :m] = c[:, :, 0:SIDE * 8:8, 0:SIDE * 8:8]
+    lev = coefficient_levels(c.shape[-1], levels)[:SIDE * 8, :SIDE * 8]
+    sq = c[:, :, :SIDE * 8, :SIDE * 8] ** 2
+    for f in range(m):
+        for lv in (1, 2, 3):
+            e = np.where(lev == lv, sq[:, f], 0.0)
+            out[:, m + 3 * f + lv - 1] = e.reshape(b, SIDE, 8, SIDE, 8).sum(axis=(2, 4))
+    return out
+
+
+def input_map(raw: np.ndarray) -> np.ndarray:
+    """The network's input map of raw features ``[B, 36, 8, 8]`` -> ``[B, 12, 8, 8]``."""
+    r = np.asarray(raw, dtype=np.float64)
+    m = C_FIELDS
+    x = np.empty((r.shape[0], C_IN, SIDE, SIDE))
+    x[:, :m] = np.arcsinh(r[:, :m] / FEATURE_SCALE)
+    for lv in range(3):
+        e = sum(r[:, m + 3 * f + lv] for f in range(m))
+        x[:, m + lv] = np.arcsinh(np.sqrt(e) / FEATURE_SCALE)
+    return x
+
+
+def features(coef: np.ndarray, levels: int = 5) -> np.ndarray:
+    """Network input of coefficient tiles ``[B, 9, s, s]`` (the input map of their raw features)."""
+    return input_map(raw_features(coef, levels))
 
 
 def choose_thresholds(pred: np.ndarray, candidates, budget_log10: np.ndarray, fallback: float) -> np.ndarray:

@@ -673,10 +673,60 @@ class CompressedRun:
         self.values = values
         if values != "f32" and self.dtype != np.float32:
             raise ValueError("narrow value formats store float32 coefficients")
+        self.eps_patch = None     # per-patch threshold constants, or None for eps
+        self.levels_patch = None  # per-patch level counts, or None for g.levels
         self.thr = threshold_table(g.s, g.levels, eps, rule, self.dtype)
         self.coef = None
         self.kept = None          # threshold decisions of the stored coefficients
         self.steps = 0
+
+    # -- per-patch threshold controls -------------------------------------------
+    def _rebuild_thresholds(self):
+        """Threshold tables: one per patch when its constant or level count is its own.
+
+        Patch q's table is that of its constant eps_q and its threshold level
+        count L_q (Section 2.2 with L_q in place of L: the L_q finest detail
+        levels may be zeroed, ranks counted from the coarsest of them, coarser
+        coefficients kept like samples).  With BL5/3 tiles a bordering line is
+        stored by both tiles that share it (Section 3.1.1); it takes, entry by
+        entry, the smaller of the two tiles' thresholds, so that both keep the
+        same coefficients of it and reconstruct the same values there (the
+        shared values the conservation of the totals rests on).  Corners are
+        samples in both dimensions and never thresholded."""
+        g = self.g
+        if self.eps_patch is None and self.levels_patch is None:
+            self.thr = threshold_table(g.s, g.levels, self.eps, self.rule, self.dtype)
+            return
+        npatch = g.npatch
+        eps = [self.eps] * npatch if self.eps_patch is None else [float(e) for e in self.eps_patch]
+        lev = [g.levels] * npatch if self.levels_patch is None else [int(L) for L in self.levels_patch]
+        base = np.stack([threshold_table(g.s, lev[q], eps[q], self.rule, self.dtype) for q in range(npatch)])
+        thr = base.copy()
+        if g.wavelet == BL53:
+            p = g.p
+            for q in range(npatch):
+                px, py = q % g.npx, q // g.npx
+                left = (px - 1) % g.npx + g.npx * py
+                right = (px + 1) % g.npx + g.npx * py
+                down = px + g.npx * ((py - 1) % g.npx)
+                up = px + g.npx * ((py + 1) % g.npx)
+                thr[q, :, 0] = np.minimum(thr[q, :, 0], base[left, :, p])
+                thr[q, :, p] = np.minimum(thr[q, :, p], base[right, :, 0])
+                thr[q, 0, :] = np.minimum(thr[q, 0, :], base[down, p, :])
+                thr[q, p, :] = np.minimum(thr[q, p, :], base[up, 0, :])
+        self.thr = thr[:, None]
+
+    def set_patch_levels(self, levels=None):
+        """One threshold level count per patch (the learned control), 0 <= L_q <= L,
+        or None for the single count L.  The transform keeps its L levels."""
+        if self.values != "f32" and levels is not None:
+            raise ValueError("per-patch level counts are for float32 records")
+        if levels is not None:
+            lv = np.asarray(levels, dtype=np.int64)
+            if np.any(lv < 0) or np.any(lv > self.g.levels):
+                raise ValueError("threshold level counts must lie in [0, L]")
+        self.levels_patch = None if levels is None else np.asarray(levels, dtype=np.int64).copy()
+        self._rebuild_thresholds()
 
     # -- compression of tiles ------------------------------------------------
     def compress_tiles(self, tiles: np.ndarray) -> np.ndarray:
@@ -705,11 +755,10 @@ class CompressedRun:
 
     def set_patch_eps(self, eps=None):
         """One threshold constant per patch (the learned control), or None for the single eps."""
-        if eps is None:
-            self.thr = threshold_table(self.g.s, self.g.levels, self.eps, self.rule, self.dtype)
-        else:
-            self.thr = np.stack([threshold_table(self.g.s, self.g.levels, float(e), self.rule, self.dtype)
-                                 for e in eps])[:, None]
+        if self.values != "f32" and eps is not None:
+            raise ValueError("per-patch thresholds are for float32 records")
+        self.eps_patch = None if eps is None else np.asarray(eps, dtype=np.float64).copy()
+        self._rebuild_thresholds()
 
     def set_coefficients(self, coef: np.ndarray, threshold: bool = True):
         c = np.asarray(coef, dtype=self.dtype)

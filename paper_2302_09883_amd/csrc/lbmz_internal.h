@@ -45,6 +45,7 @@ struct PatchArgs {
   int rule;          // Rule
   double eps;        // threshold constant
   const double* eps_patch;       // per-patch threshold constants [npatch], or null for eps
+  const int8_t* lev_patch;       // per-patch threshold level counts [npatch] (<= levels), or null for levels
   float* features;               // per-patch stride-8 coefficients [npatch][M][8][8], or null
   // scheme
   double dt_over_h;  // FV

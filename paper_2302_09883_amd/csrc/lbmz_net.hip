@@ -3,9 +3,13 @@
 // kernels below (one workgroup per sample for the forward pass, one per group
 // of samples for the gradients, a fixed-order reduction, an Adam update).
 //
-//   input  x[9][8][8]: a patch's stored coefficients at the owned positions of
-//          stride 8, mapped by asinh(c / 1e-4)
-//   conv1  3x3, pad 1, 9 -> 32, bias, ReLU        (8 x 8)
+//   input  x[36][8][8], the patch features of the step kernel: channels 0..8
+//          a patch's stored coefficients at the owned positions of stride 8,
+//          channels 9 + 3 f + l - 1 the energy of field f's level-l
+//          coefficients (l = 1, 2, 3) in each 8 x 8 block;
+//          mapped to 12 channels: asinh(c / 1e-4) of the 9 coefficients and
+//          asinh(sqrt(sum over the fields of the level-l energy) / 1e-4)
+//   conv1  3x3, pad 1, 12 -> 32, bias, ReLU       (8 x 8)
 //   conv2  3x3, pad 1, 32 -> 32, bias, ReLU       (8 x 8)
 //   conv3  3x3, pad 1, stride 2, 32 -> 32, ReLU   (4 x 4)
 //   pool   mean over the 16 positions
@@ -26,7 +30,9 @@
 
 namespace lbmz_net_impl {
 
-constexpr int CI = 9, CH = 32, KMAX = 16;
+constexpr int CF = 9;                      // fields of the patch (coefficient channels)
+constexpr int CIN = 4 * CF;                // channels of one input sample (the patch features)
+constexpr int CI = CF + 3, CH = 32, KMAX = 32;
 constexpr int NT = 256;
 constexpr int OW1 = 0, OB1 = OW1 + CH * CI * 9, OW2 = OB1 + CH, OB2 = OW2 + CH * CH * 9, OW3 = OB2 + CH,
               OB3 = OW3 + CH * CH * 9, OWH = OB3 + CH;   // head weights at OWH, head biases at OWH + 32 K
@@ -57,7 +63,18 @@ struct Acts {
 // Forward pass of one sample into the activation buffers (pre-ReLU values).
 __device__ void forward_sample(const uint16_t* w, const float* xin_raw, int k, Acts& s) {
   const int tid = threadIdx.x;
-  for (int i = tid; i < CI * 64; i += NT) s.x[i] = asinhf(xin_raw[i] * FSCALE);
+  for (int i = tid; i < CI * 64; i += NT) {
+    const int c = i / 64, pos = i - 64 * c;
+    float v;
+    if (c < CF) {
+      v = xin_raw[i];
+    } else {
+      float e = 0.0f;   // level c - CF + 1, summed over the fields in field order
+      for (int f = 0; f < CF; ++f) e += xin_raw[(CF + 3 * f + (c - CF)) * 64 + pos];
+      v = sqrtf(e);
+    }
+    s.x[i] = asinhf(v * FSCALE);
+  }
   __syncthreads();
   for (int idx = tid; idx < CH * 64; idx += NT) {
     const int o = idx >> 6, p = idx & 63, i = p >> 3, j = p & 7;
@@ -126,7 +143,7 @@ __global__ __launch_bounds__(NT) void net_forward_kernel(const uint16_t* __restr
   const int np = nparams(k);
   for (int i = threadIdx.x; i < np; i += NT) w[i] = wbf[i];
   __syncthreads();
-  forward_sample(w, x + (size_t)blockIdx.x * CI * 64, k, s);
+  forward_sample(w, x + (size_t)blockIdx.x * CIN * 64, k, s);
   if (threadIdx.x < k) y[(size_t)blockIdx.x * k + threadIdx.x] = s.y[threadIdx.x];
 }
 
@@ -153,7 +170,7 @@ __global__ __launch_bounds__(NT) void net_grad_kernel(const uint16_t* __restrict
   const float scale = 2.0f / ((float)batch * (float)k);
   __syncthreads();
   for (int b = blockIdx.x * SPW; b < batch && b < (int)(blockIdx.x + 1) * SPW; ++b) {
-    forward_sample(w, x + (size_t)b * CI * 64, k, s);
+    forward_sample(w, x + (size_t)b * CIN * 64, k, s);
     if (tid < k) {
       const float d = s.y[tid] - t[(size_t)b * k + tid];
       dy[tid] = scale * d;
@@ -388,7 +405,7 @@ int ensure_part(lbmz_net* n, size_t blocks) {
 int batch_gradients(lbmz_net* n, const float* x, const float* t, int batch, int on_device, float* loss) {
   const float* xd = x;
   const float* td = t;
-  const size_t xb = (size_t)batch * CI * 64 * sizeof(float), tb = (size_t)batch * n->k * sizeof(float);
+  const size_t xb = (size_t)batch * CIN * 64 * sizeof(float), tb = (size_t)batch * n->k * sizeof(float);
   if (!on_device) {
     int rc = ensure_io(n, xb + tb);
     if (rc) return rc;
@@ -487,7 +504,7 @@ int lbmz_net_get_params(lbmz_net* n, float* params, size_t count) {
 int lbmz_net_forward(lbmz_net* n, const float* x, int batch, float* y, int on_device) {
   if (!n || !x || !y || batch < 0) return LBMZ_EINVAL;
   if (batch == 0) return LBMZ_OK;
-  const size_t xb = (size_t)batch * CI * 64 * sizeof(float), yb = (size_t)batch * n->k * sizeof(float);
+  const size_t xb = (size_t)batch * CIN * 64 * sizeof(float), yb = (size_t)batch * n->k * sizeof(float);
   const float* xd = x;
   float* yd = y;
   if (!on_device) {

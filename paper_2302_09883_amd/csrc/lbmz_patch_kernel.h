@@ -414,9 +414,116 @@ __device__ __forceinline__ void threshold_column(T* v, int x, int L, T eps, int 
   }
 }
 
+// Periodic index of a patch coordinate (v within one period of [0, n)).
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
 // Threshold constant of patch q: the per-patch value when one is set.
 __device__ __forceinline__ double patch_eps(const PatchArgs& a, int q) {
   return a.eps_patch ? a.eps_patch[q] : a.eps;
+}
+
+// Threshold level count of patch q: the L_q finest detail levels may be
+// zeroed, with ranks counted from the coarsest of them (Section 2.2 with L_q
+// in place of L); coarser coefficients are kept like samples.
+__device__ __forceinline__ int patch_thr_levels(const PatchArgs& a, int q) {
+  return a.lev_patch ? (int)a.lev_patch[q] : a.levels;
+}
+
+// Threshold of patch q's column x for level class k of y (see threshold_column).
+template <class C, class T>
+__device__ __forceinline__ T class_threshold(int x, int k, T eps, int lq, int rule) {
+  return thr_of<T>(dim_rank(x, lq), (k > lq) ? -1 : lq - k, eps, rule);
+}
+
+// Hard threshold of column x of patch q with per-patch controls.  The
+// column's own thresholds come from the patch's constant and level count.
+// With BL5/3 tiles a bordering line is stored by both tiles that share it
+// (Section 3.1.1), so it takes, entry by entry, the smaller of the two tiles'
+// thresholds: both keep the same coefficients of it and reconstruct the same
+// shared values, on which the conservation of the totals rests.  The columns
+// x = 0 and x = P are shared with the left and right neighbours, the entries
+// y = 0 and y = P with the lower and upper ones (corners are samples).
+template <class C, class T>
+__device__ __forceinline__ void threshold_patch_column(const PatchArgs& a, int q, T* v, int x, int L) {
+  if (!a.eps_patch && !a.lev_patch) {
+    threshold_column<C, T>(v, x, L, T(a.eps), a.rule);
+    return;
+  }
+  const int rule = a.rule;
+  const T e0 = T(patch_eps(a, q));
+  const int l0 = patch_thr_levels(a, q);
+  T tl[C::LMAX + 2];
+#pragma unroll
+  for (int k = 1; k <= C::LMAX + 1; ++k) tl[k] = class_threshold<C, T>(x, k, e0, l0, rule);
+  T row0 = tl[C::LMAX + 1], rowp = tl[C::LMAX + 1];   // y = 0 and y = P: sample rows
+  if constexpr (C::RIM) {
+    const int px = q % a.npx, py = q / a.npx;
+    if (x == 0 || x == C::P) {
+      const int nb = wrap(px + (x == 0 ? -1 : 1), a.npx) + a.npx * py;
+      const T e1 = T(patch_eps(a, nb));
+      const int l1 = patch_thr_levels(a, nb);
+#pragma unroll
+      for (int k = 1; k <= C::LMAX + 1; ++k) tl[k] = fmin(tl[k], class_threshold<C, T>(x, k, e1, l1, rule));
+      row0 = tl[C::LMAX + 1];
+      rowp = tl[C::LMAX + 1];
+    }
+    const int dn = px + a.npx * wrap(py - 1, a.npx);
+    const int upn = px + a.npx * wrap(py + 1, a.npx);
+    row0 = fmin(row0, class_threshold<C, T>(x, C::LMAX + 1, T(patch_eps(a, dn)), patch_thr_levels(a, dn), rule));
+    rowp = fmin(rowp, class_threshold<C, T>(x, C::LMAX + 1, T(patch_eps(a, upn)), patch_thr_levels(a, upn), rule));
+  }
+#pragma unroll
+  for (int y = 0; y < C::S; ++y) {
+    T thr = tl[level_class<C::LMAX>(y)];
+    if (y == 0) thr = row0;
+    if (C::RIM && y == C::S - 1) thr = rowp;
+    v[y] = (fabs(v[y]) < thr) ? T(0) : v[y];
+  }
+}
+
+// Network input of patch q, per patch 4 M channels of 8 x 8 (64 x 64
+// patches): channel f the stored coefficients of field f at the owned
+// positions of stride 8 (written from the column of lane x = 8 i), channel
+// M + 3 f + l - 1 the energy (sum of squares, before the threshold) of field
+// f's coefficients of level l = 1, 2, 3 in each 8 x 8 block of owned
+// positions.  The level of coefficient (x, y) is the finer of its two
+// per-dimension levels (a sample index counts as coarser than any level);
+// every coefficient of a block but the one at its stride-8 corner has a level
+// of at most 3, the levels the stride-8 view does not hold.
+constexpr int FEAT_CH_PER_FIELD = 4;
+
+// Energies of column x (its coefficients before the threshold in v), by 8 x 8
+// block and level; called by whole field waves (lane = column x < 64).  The
+// eight lanes of a block add their sums by a fixed butterfly.
+template <class C, class T>
+__device__ __forceinline__ void export_energies(const PatchArgs& a, int q, int f, int x, const T* v, int L) {
+  if constexpr (C::P == 64) {
+    const int lm = (1 << L) - 1;
+    const int cx = (x & lm) == 0 ? 64 : 1 + __builtin_ctz((unsigned)x);
+    float* dst = a.features + ((size_t)q * FEAT_CH_PER_FIELD * C::M + C::M + 3 * f) * 64;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      float e[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int yy = 0; yy < 8; ++yy) {
+        const int y = 8 * j + yy;
+        const int cy = (y & lm) == 0 ? 64 : 1 + __builtin_ctz((unsigned)(y == 0 ? 1 : y));
+        const int l = cx < cy ? cx : cy;
+        const float c = (float)v[y];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) e[k] = fmaf(l == k + 1 ? c : 0.f, c, e[k]);
+      }
+#pragma unroll
+      for (int d = 1; d < 8; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) e[k] += __shfl_xor(e[k], d, 64);
+      }
+      if ((x & 7) == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dst[k * 64 + 8 * j + (x >> 3)] = e[k];
+      }
+    }
+  }
 }
 
 // Network input of patch q: the stored coefficients of the owned positions
@@ -425,7 +532,7 @@ template <class C, class T>
 __device__ __forceinline__ void export_features(const PatchArgs& a, int q, int f, int x, const T* v) {
   if constexpr (C::P == 64) {
     if (a.features && (x & 7) == 0 && x < C::P) {
-      float* dst = a.features + ((size_t)q * C::M + f) * 64 + (x >> 3);
+      float* dst = a.features + ((size_t)q * FEAT_CH_PER_FIELD * C::M + f) * 64 + (x >> 3);
 #pragma unroll
       for (int i = 0; i < 8; ++i) dst[8 * i] = (float)v[8 * i];
     }
@@ -509,7 +616,6 @@ __device__ __forceinline__ void totals_finish(const PatchArgs& a, double* out, i
 // one, N <- line y = LO of the north one.  For D2Q9 only the three
 // populations streaming into the neighbour are kept; for FV every field.
 
-__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // D2Q9: W/E strips (rows 0..S-1) for the x shift of the row pass, and the
 // S/N ghost rows of the tile, already shifted in x: row -1 of population i
@@ -1160,7 +1266,8 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm
   if (act) {
     load_col<C>(v, sm.tile, field_base<C>(f), x);
     if constexpr (FWD) LF::fwd(v, L);
-    threshold_column<C, T>(v, x, L, T(patch_eps(a, q)), a.rule);
+    if (a.features && wave < C::M) export_energies<C, T>(a, q, f, x, v, L);
+    threshold_patch_column<C, T>(a, q, v, x, L);
     if constexpr (!FWD) {
       // Given coefficients: a scaled sum of magnitudes stays finite for any
       // finite column and turns into Inf / NaN with any non-finite element.

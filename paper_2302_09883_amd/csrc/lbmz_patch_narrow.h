@@ -158,7 +158,7 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
   if (act) {
     load_col<C>(v, sm.tile, field_base<C>(f), x);
     if constexpr (FWD) LF::fwd(v, L);
-    threshold_column<C, T>(v, x, L, T(patch_eps(a, q)), a.rule);
+    threshold_column<C, T>(v, x, L, T(a.eps), a.rule);
     if constexpr (!FWD) {
 #pragma unroll
       for (int y = 0; y < C::S; ++y) mag = fma(fabs(v[y]), T(0x1p-64), mag);
@@ -256,7 +256,7 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
     // bounded format: bit g of f16need when field g's record needs binary16
     uint32_t f16need = 0u;
     if constexpr (VF == VF_E4M3B) {
-      const float epsq = (float)patch_eps(a, q);
+      const float epsq = (float)a.eps;
       for (int i = lane; i < C::M * nb; i += 64) {
         const int g = i / nb;
         const int b = i - g * nb;

@@ -113,6 +113,7 @@ struct lbmz_ctx {
   int graph_mode[2] = {-1, -1};                  // exec_persistent at instantiation
   PatchArgs gargs[6] = {};
   double* eps_patch = nullptr;   // per-patch thresholds (device), or null
+  int8_t* lev_patch = nullptr;   // per-patch threshold level counts (device), or null
   float* features = nullptr;     // per-patch network inputs of the last step (device), or null
   bool features_valid = false;
   int nfields = 1, nslot = 1;
@@ -331,6 +332,7 @@ PatchArgs args_for(lbmz_ctx* c, int in, int out, unsigned epoch) {
   a.ctrl = c->ctrl;
   a.epoch = epoch;
   a.eps_patch = c->eps_patch;
+  a.lev_patch = c->lev_patch;
   a.features = c->features;
   a.scratch = c->scratch;
   return a;
@@ -1171,6 +1173,7 @@ int lbmz_set_patch_eps(lbmz_ctx* c, const double* eps, size_t count, int on_devi
   }
   if (!eps) return LBMZ_EINVAL;
   if (c->dim == 3) return fail(c, LBMZ_EINVAL, "per-patch thresholds are for 2-D grids");
+  if (c->vf != VF_F32) return fail(c, LBMZ_EINVAL, "per-patch thresholds need float32 records");
   if (count != (size_t)c->npatch)
     return fail(c, LBMZ_EINVAL, "expected %d per-patch thresholds, got %zu", c->npatch, count);
   if (!on_device) {
@@ -1185,13 +1188,43 @@ int lbmz_set_patch_eps(lbmz_ctx* c, const double* eps, size_t count, int on_devi
   return copy_in(c, c->eps_patch, eps, count * sizeof(double), on_device);
 }
 
+int lbmz_set_patch_levels(lbmz_ctx* c, const int* levels, size_t count) {
+  if (!c) return LBMZ_EINVAL;
+  if (c->reference) return fail(c, LBMZ_ESTATE, "a reference context has no threshold");
+  if (count == 0) {
+    if (c->lev_patch) {
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      dfree(c, c->lev_patch);
+      c->lev_patch = nullptr;
+    }
+    return LBMZ_OK;
+  }
+  if (!levels) return LBMZ_EINVAL;
+  if (c->dim == 3) return fail(c, LBMZ_EINVAL, "per-patch level counts are for 2-D grids");
+  if (c->vf != VF_F32) return fail(c, LBMZ_EINVAL, "per-patch level counts need float32 records");
+  if (count != (size_t)c->npatch)
+    return fail(c, LBMZ_EINVAL, "expected %d per-patch level counts, got %zu", c->npatch, count);
+  std::vector<int8_t> lv(count);
+  for (size_t q = 0; q < count; ++q) {
+    if (levels[q] < 0 || levels[q] > c->levels)
+      return fail(c, LBMZ_EINVAL, "level count %d of patch %zu outside [0, %d]", levels[q], q, c->levels);
+    lv[q] = (int8_t)levels[q];
+  }
+  if (!c->lev_patch) {
+    c->lev_patch = static_cast<int8_t*>(dalloc(c, count));
+    if (!c->lev_patch) return fail(c, LBMZ_ENOMEM, "per-patch level allocation failed");
+  }
+  return copy_in(c, c->lev_patch, lv.data(), count, 0);
+}
+
 int lbmz_enable_features(lbmz_ctx* c, int on) {
   if (!c) return LBMZ_EINVAL;
   if (c->reference) return fail(c, LBMZ_ESTATE, "a reference context has no coefficients");
   if (on) {
     if (c->p != 64) return fail(c, LBMZ_EINVAL, "patch features need 64 x 64 patches");
+    if (c->dim != 2 || c->vf != VF_F32) return fail(c, LBMZ_EINVAL, "patch features need 2-D float32 records");
     if (!c->features) {
-      c->features = static_cast<float*>(dalloc(c, (size_t)c->npatch * c->nfields * 64 * sizeof(float)));
+      c->features = static_cast<float*>(dalloc(c, (size_t)c->npatch * c->nfields * 4 * 64 * sizeof(float)));
       if (!c->features) return fail(c, LBMZ_ENOMEM, "feature buffer allocation failed");
     }
   } else if (c->features) {
@@ -1207,7 +1240,7 @@ int lbmz_get_features(lbmz_ctx* c, float* dst, size_t bytes, int dst_on_device) 
   if (!c || !dst) return LBMZ_EINVAL;
   if (!c->features) return fail(c, LBMZ_ESTATE, "features are not enabled");
   if (!c->features_valid) return fail(c, LBMZ_ESTATE, "no step has written the features yet");
-  const size_t want = (size_t)c->npatch * c->nfields * 64 * sizeof(float);
+  const size_t want = (size_t)c->npatch * c->nfields * 4 * 64 * sizeof(float);
   if (bytes != want) return fail(c, LBMZ_EINVAL, "expected %zu bytes of features, got %zu", want, bytes);
   HIPCHK(c, hipMemcpyAsync(dst, c->features, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                            c->stream));
@@ -1281,6 +1314,7 @@ void lbmz_destroy(lbmz_ctx* c) {
   dfree(c, c->ctrl);
   dfree(c, c->scratch);
   dfree(c, c->eps_patch);
+  dfree(c, c->lev_patch);
   dfree(c, c->features);
   if (c->ctrl_host) (void)hipHostFree(c->ctrl_host);
   if (c->ev0) (void)hipEventDestroy(c->ev0);

@@ -68,6 +68,13 @@ def library() -> ct.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "or python -m paper_2302_09883_amd.build")
+    # PyTorch (the device-memory and stream plumbing) ships its own HIP
+    # runtime; loading it first makes the library bind to that same runtime,
+    # so that both share one device context in this process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ct.CDLL(LIB_PATH)
     P = ct.POINTER
     vp = ct.c_void_p
@@ -92,6 +99,7 @@ def library() -> ct.CDLL:
         "lbmz_get_execution": ([vp, P(ct.c_int), P(ct.c_int)], ct.c_int),
         "lbmz_autotune": ([vp, ct.c_int, vp], ct.c_int),
         "lbmz_set_patch_eps": ([vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
+        "lbmz_set_patch_levels": ([vp, vp, ct.c_size_t], ct.c_int),
         "lbmz_enable_features": ([vp, ct.c_int], ct.c_int),
         "lbmz_get_features": ([vp, vp, ct.c_size_t, ct.c_int], ct.c_int),
         "lbmz_last_error": ([vp], ct.c_char_p),
@@ -262,14 +270,23 @@ class Context:
         self._check(self._lib.lbmz_set_patch_eps(self._h, ptr, nb // 8, dev))
         del keep
 
+    def set_patch_levels(self, levels=None):
+        """One level count per patch (the learned control), or None for the context's single count."""
+        if levels is None:
+            self._check(self._lib.lbmz_set_patch_levels(self._h, None, 0))
+            return
+        a = np.ascontiguousarray(levels, dtype=np.int32)
+        self._check(self._lib.lbmz_set_patch_levels(self._h, ct.c_void_p(a.ctypes.data), a.size))
+
     def enable_features(self, on: bool = True):
         self._check(self._lib.lbmz_enable_features(self._h, int(bool(on))))
 
     def features(self, out=None):
-        """Network inputs of the last step, ``float32 [npatch, nfields, 8, 8]`` (host unless ``out`` is a device tensor)."""
+        """Network inputs of the last step, ``float32 [npatch, 4 nfields, 8, 8]`` (host unless ``out``
+        is a device tensor): the stride-8 coefficients, then per field the level 1, 2, 3 energies."""
         npatch = (self.n // self.p) ** 2
         if out is None:
-            out = np.empty((npatch, self.nfields, 8, 8), dtype=np.float32)
+            out = np.empty((npatch, 4 * self.nfields, 8, 8), dtype=np.float32)
         ptr, nb, dev, keep = _buffer(out, np.float32)
         self._check(self._lib.lbmz_get_features(self._h, ptr, nb, dev))
         return out
@@ -365,7 +382,7 @@ class Net:
 
     def forward(self, x, out=None):
         ptr, nb, dev, keep = _buffer(x, np.float32)
-        batch = nb // (9 * 64 * 4)
+        batch = nb // (36 * 64 * 4)
         if out is None:
             out = np.empty((batch, self.k), dtype=np.float32)
         optr, _, odev, okeep = _buffer(out, np.float32)
@@ -398,7 +415,7 @@ class Net:
         xp, xb, xdev, xk = _buffer(x, np.float32)
         tp, tb, tdev, tk = _buffer(t, np.float32)
         loss = ct.c_float()
-        self._check(self._lib.lbmz_net_train_step(self._h, xp, tp, xb // (9 * 64 * 4), ct.c_float(lr),
+        self._check(self._lib.lbmz_net_train_step(self._h, xp, tp, xb // (36 * 64 * 4), ct.c_float(lr),
                                                   ct.byref(loss), xdev))
         return float(loss.value)
 

@@ -106,3 +106,20 @@ def test_autotune_keeps_the_trajectory():
     base.step(9)
     _same(base, tuned)
     print("[case] autotune ms/step (plain, graph, persistent, both):", ms.tolist(), "chose", tuned.execution())
+
+
+def test_patch_shape_tuner_compares_at_equal_error():
+    """The patch-shape tuner measures every compiled shape of the D2Q9
+    workload (speed, ratio, error against the uncompressed run of the same
+    length) and keeps the fastest one whose error is within its tolerance of
+    the smallest error."""
+    from paper_2302_09883_amd.execution import SHAPES, tune_patch_shape
+    print("[case] patch-shape tuner", flush=True)
+    res = tune_patch_shape(n=256, eps=1e-4, steps=10, tune_steps=1)
+    assert [(r["patch"], r["levels"]) for r in res["shapes"]] == list(SHAPES)
+    for r in res["shapes"]:
+        assert r["mlups_events"] > 0 and r["ratio"] > 1 and 0 < r["rel_l2"] < 1e-2
+    best = min(r["rel_l2"] for r in res["shapes"])
+    ok = [r for r in res["shapes"] if r["rel_l2"] <= (1 + res["tolerance"]) * best]
+    fastest = max(ok, key=lambda r: r["mlups_events"])
+    assert (res["chosen"]["patch"], res["chosen"]["levels"]) == (fastest["patch"], fastest["levels"])

@@ -36,8 +36,10 @@ def test_conv_matches_loops(stride):
 
 
 def test_parameter_count():
-    shapes = N.param_shapes(6)
-    assert sum(int(np.prod(s)) for s in shapes.values()) == 21318
+    # 12 input channels (9 coefficient maps, 3 level-energy maps), 32 hidden
+    shapes = N.param_shapes(12)
+    assert sum(int(np.prod(s)) for s in shapes.values()) == 32 * 12 * 9 + 32 + 2 * (32 * 32 * 9 + 32) + 33 * 12
+    assert sum(int(np.prod(s)) for s in shapes.values()) == 22380
 
 
 def test_gradients_against_finite_differences():
@@ -106,3 +108,47 @@ def test_choose_thresholds():
     pred = np.array([[-9.0, -8.0, -7.0], [-6.0, -5.0, -4.0]])
     eps = N.choose_thresholds(pred, [1e-5, 1e-4, 1e-3], np.array([-7.5, -7.5]), fallback=3e-5)
     assert eps[0] == 1e-4 and eps[1] == 3e-5
+
+
+def test_coefficient_levels_by_definition():
+    s, L = 65, 5
+    lev = N.coefficient_levels(s, L)
+    for y in range(s):
+        for x in range(s):
+            def dim(i):
+                if i % (1 << L) == 0:
+                    return L + 1
+                k = 0
+                while i % 2 == 0:
+                    i //= 2
+                    k += 1
+                return k + 1
+            assert lev[y, x] == min(dim(x), dim(y))
+    # an 8 x 8 block holds its stride-8 corner plus coefficients of levels 1..3 only
+    blk = lev[8:16, 16:24]
+    assert blk[0, 0] > 3 and np.all(blk.reshape(-1)[1:] <= 3)
+
+
+def test_raw_features_by_brute_force():
+    rng = np.random.default_rng(7)
+    coef = rng.standard_normal((2, 9, 65, 65))
+    raw = N.raw_features(coef, 5)
+    assert raw.shape == (2, 36, 8, 8)
+    lev = N.coefficient_levels(65, 5)
+    for b in range(2):
+        for f in (0, 4, 8):
+            for j in range(8):
+                for i in range(8):
+                    assert raw[b, f, j, i] == coef[b, f, 8 * j, 8 * i]
+                    for lv in (1, 2, 3):
+                        e = 0.0
+                        for y in range(8 * j, 8 * j + 8):
+                            for x in range(8 * i, 8 * i + 8):
+                                if lev[y, x] == lv:
+                                    e += coef[b, f, y, x] ** 2
+                        assert abs(raw[b, 9 + 3 * f + lv - 1, j, i] - e) <= 1e-12 * max(e, 1.0)
+    x = N.input_map(raw)
+    assert x.shape == (2, 12, 8, 8)
+    assert np.allclose(x[:, :9], np.arcsinh(coef[:, :, 0:64:8, 0:64:8] / 1e-4))
+    e2 = sum(raw[:, 9 + 3 * f + 1] for f in range(9))
+    assert np.allclose(x[:, 10], np.arcsinh(np.sqrt(e2) / 1e-4))

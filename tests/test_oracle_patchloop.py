@@ -128,3 +128,109 @@ def test_patch_order_does_not_matter():
         coef[q] = run.compress_tiles(run.scheme.update(padded[q:q + 1]))[0]
     run.step()
     assert np.array_equal(coef, run.coef)
+
+
+# ---------------------------------------------------------------- per-patch controls
+
+def _controls(g, seed=0):
+    """Mixed per-patch threshold constants and threshold level counts."""
+    rng = np.random.default_rng(seed)
+    eps = 10.0 ** rng.uniform(-5, -3, g.npatch)
+    lev = rng.integers(max(g.levels - 2, 0), g.levels + 1, size=g.npatch)
+    return eps, lev
+
+
+@pytest.mark.parametrize("kind,wavelet,n,p,L,eps", CASES)
+def test_uniform_controls_change_nothing(kind, wavelet, n, p, L, eps):
+    g = O.Geometry(n, p, wavelet, L)
+    a = O.CompressedRun(g, _scheme(kind), eps)
+    b = O.CompressedRun(g, _scheme(kind), eps)
+    b.set_patch_eps(np.full(g.npatch, eps))
+    b.set_patch_levels(np.full(g.npatch, L))
+    init = _initial(kind, n)
+    a.set_grid(init)
+    b.set_grid(init)
+    for _ in range(3):
+        a.step()
+        b.step()
+    assert np.array_equal(a.coef, b.coef)
+
+
+@pytest.mark.parametrize("kind,wavelet,n,p,L,eps", CASES)
+def test_mixed_controls_keep_shared_faces_and_the_protocol(kind, wavelet, n, p, L, eps):
+    # per-patch constants and level counts: the shared bordering lines take the
+    # smaller threshold of their two tiles, so both tiles reconstruct the same
+    # values there, the patch loop still equals the whole-grid protocol bit for
+    # bit, and the global total is conserved
+    g = O.Geometry(n, p, wavelet, L)
+    e, lev = _controls(g, seed=n + p)
+    runs = []
+    for _ in range(2):
+        r = O.CompressedRun(g, _scheme(kind), eps)
+        r.set_patch_eps(e)
+        r.set_patch_levels(lev)
+        r.set_grid(_initial(kind, n))
+        runs.append(r)
+    a, b = runs
+    m0 = a.field_totals()
+    for _ in range(4):
+        a.step()
+        O.whole_grid_step(b)
+        assert np.array_equal(a.coef, b.coef)
+    m1 = a.field_totals()
+    if kind == "d2q9_bgk":          # mass and momentum of the populations
+        c = O.D2Q9_C
+        m0 = np.array([m0.sum(), (c[:, 0] * m0).sum(), (c[:, 1] * m0).sum()])
+        m1 = np.array([m1.sum(), (c[:, 0] * m1).sum(), (c[:, 1] * m1).sum()])
+    assert np.all(np.abs(m1 - m0) <= 1e-13 * np.abs(m0).sum())
+    if wavelet == O.BL53:
+        lossy = a.decompress_tiles()
+        for py in range(g.npx):
+            for px in range(g.npx):
+                q = px + g.npx * py
+                right = ((px + 1) % g.npx) + g.npx * py
+                up = px + g.npx * ((py + 1) % g.npx)
+                assert np.array_equal(lossy[q][:, :, p], lossy[right][:, :, 0])
+                assert np.array_equal(lossy[q][:, p, :], lossy[up][:, 0, :])
+
+
+def test_face_thresholds_are_the_smaller_of_the_two_tiles():
+    g = O.Geometry(64, 16, O.BL53, 3)
+    r = O.CompressedRun(g, _scheme("d2q9_bgk"), 1e-4)
+    e, lev = _controls(g, seed=5)
+    r.set_patch_eps(e)
+    r.set_patch_levels(lev)
+    base = [O.threshold_table(g.s, int(lev[q]), float(e[q]), O.RULE_CAPPED, np.float64) for q in range(g.npatch)]
+    q, right, up = 5, 6, 9                                    # px = 1, py = 1 on the 4 x 4 patch grid
+    thr = r.thr[:, 0]
+    assert np.array_equal(thr[q][1:-1, 1:-1], base[q][1:-1, 1:-1])      # interior: the patch's own table
+    assert np.array_equal(thr[q][:, 16], np.minimum(base[q][:, 16], base[right][:, 0]))
+    assert np.array_equal(thr[q][16, :], np.minimum(base[q][16, :], base[up][0, :]))
+    assert np.array_equal(thr[q][:, 16], thr[right][:, 0])               # one threshold per shared entry
+    assert thr[q][0, 0] == 0 and thr[q][16, 16] == 0                      # corners are samples
+
+
+def test_level_count_semantics():
+    # L_q = 0 zeroes nothing; a smaller level count thresholds fewer levels,
+    # with ranks counted from the coarsest thresholded one
+    s, L, eps = 17, 3, 1e-3
+    t0 = O.threshold_table(s, 0, eps, O.RULE_CAPPED, np.float64)
+    assert np.all(t0 == 0)
+    t3 = O.threshold_table(s, 3, eps, O.RULE_CAPPED, np.float64)
+    t2 = O.threshold_table(s, 2, eps, O.RULE_CAPPED, np.float64)
+    assert t3[0, 1] == eps * 4 and t2[0, 1] == eps * 2          # finest detail: rank L_q - 1
+    assert t3[0, 4] == eps * 1 and t2[0, 4] == 0                # level 3 kept like a sample at L_q = 2
+    assert np.all(t2 <= t3)
+
+
+def test_smaller_level_counts_keep_more_coefficients():
+    kind, wavelet, n, p, L, eps = CASES[2]
+    g = O.Geometry(n, p, wavelet, L)
+    kept = []
+    for lv in (L, L - 1, L - 2, 0):
+        r = O.CompressedRun(g, _scheme(kind), eps)
+        r.set_patch_levels(np.full(g.npatch, lv))
+        r.set_grid(_initial(kind, n))
+        kept.append(int(r.nnz().sum()))
+    assert kept[0] < kept[1] < kept[2] < kept[3]
+    assert kept[3] == int(np.count_nonzero(r.coef))

@@ -25,8 +25,9 @@ def _say(*args):
 
 def _batch(b, k, seed):
     rng = np.random.default_rng(seed)
-    x = (rng.standard_normal((b, 9, 8, 8)) * 10.0 ** rng.uniform(-6, -1, (b, 9, 8, 8))).astype(np.float32)
+    x = (rng.standard_normal((b, 36, 8, 8)) * 10.0 ** rng.uniform(-6, -1, (b, 36, 8, 8))).astype(np.float32)
     x[rng.random(x.shape) < 0.3] = 0
+    x[:, 9:] = x[:, 9:] ** 2          # the level energies are sums of squares
     t = rng.uniform(-12.0, -4.0, (b, k)).astype(np.float32)
     return x, t
 
@@ -56,8 +57,13 @@ def test_gradients_noalloc_equal_the_allocating_entry_point():
         assert np.all(np.isfinite(g)) and np.isfinite(loss)
         assert np.array_equal(g, g_ref), float(np.max(np.abs(g - g_ref)))
         assert loss == loss_ref
-    # above the fixed workspace: a clear error, nothing launched
-    big = 3200
+    # above the fixed workspace: a clear error, nothing launched.  The limit:
+    # ceil(B / 16) workgroups of 4 * nparams bytes (rounded up to 256) plus 4 bytes each
+    blocks = (16 << 20) // (4 * net.nparams)
+    while blocks > 0 and ((blocks * 4 * net.nparams + 255) // 256 * 256 + 4 * blocks) > (16 << 20):
+        blocks -= 1
+    limit = 16 * blocks
+    big = limit + 16
     x, t = _batch(big, k, 13)
     xd = torch.from_numpy(x).to(dev)
     td = torch.from_numpy(t).to(dev)
@@ -65,5 +71,5 @@ def test_gradients_noalloc_equal_the_allocating_entry_point():
     ld = torch.zeros(1, dtype=torch.float32, device=dev)
     with pytest.raises(LbmzError) as err:
         net.gradients_noalloc(xd, td, gd, ld)
-    assert err.value.code == LBMZ_EINVAL and "batch <= 3104" in str(err.value)
+    assert err.value.code == LBMZ_EINVAL and f"batch <= {limit}" in str(err.value)
     net.close()
