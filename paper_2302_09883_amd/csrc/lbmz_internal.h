@@ -83,17 +83,22 @@ struct KernelKey {
   int vf;      // ValueFormat
 };
 
-// Launch the fused step kernel (time n -> n + 1) or the auxiliary kernel.
-// Return hipErrorInvalidValue when no kernel is compiled for the key.
-hipError_t launch_step(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s);
-hipError_t launch_step_persistent(const KernelKey& k, const PatchArgs& a, int grid, hipStream_t s);
+// Flag of the dispatch operations that selects the step kernels with
+// per-patch controls (per-patch thresholds or level counts, network input).
+constexpr int OP_CTL = 0x100;
+
+// Launch the fused step kernel (time n -> n + 1) or the auxiliary kernel;
+// `ctl` selects the step kernel with per-patch controls.  Return
+// hipErrorInvalidValue when no kernel is compiled for the key.
+hipError_t launch_step(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s, bool ctl);
+hipError_t launch_step_persistent(const KernelKey& k, const PatchArgs& a, int grid, hipStream_t s, bool ctl);
 hipError_t launch_aux(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s);
 bool have_kernel(const KernelKey& k);
 // LDS bytes used by the kernels of a key (0 if not compiled).
 size_t kernel_lds_bytes(const KernelKey& k);
 // Entry of the step kernel (persistent or one workgroup per patch) and its
 // workgroup size, for graph kernel nodes.
-const void* step_kernel_entry(const KernelKey& k, bool persistent);
+const void* step_kernel_entry(const KernelKey& k, bool persistent, bool ctl);
 int kernel_threads(const KernelKey& k);
 
 // Dispatch of one compiled kernel family: true when the key is compiled in

@@ -1248,7 +1248,9 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
 // Returns false (uniformly) when the pool overflowed; the records are then
 // not written and the host replays the step with a larger pool.
 
-template <class C, class T, int WAV, bool FWD, class SM>
+// CTL selects the variant with per-patch controls and the network input
+// export; without it the threshold is the uniform one of the context.
+template <class C, class T, int WAV, bool FWD, bool CTL, class SM>
 __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
   static_assert(sizeof(sm.ghost) >= sizeof(T) * C::M * C::S, "shared-column staging does not fit");
@@ -1266,8 +1268,12 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm
   if (act) {
     load_col<C>(v, sm.tile, field_base<C>(f), x);
     if constexpr (FWD) LF::fwd(v, L);
-    if (a.features && wave < C::M) export_energies<C, T>(a, q, f, x, v, L);
-    threshold_patch_column<C, T>(a, q, v, x, L);
+    if constexpr (CTL) {
+      if (a.features && wave < C::M) export_energies<C, T>(a, q, f, x, v, L);
+      threshold_patch_column<C, T>(a, q, v, x, L);
+    } else {
+      threshold_column<C, T>(v, x, L, T(a.eps), a.rule);
+    }
     if constexpr (!FWD) {
       // Given coefficients: a scaled sum of magnitudes stays finite for any
       // finite column and turns into Inf / NaN with any non-finite element.
@@ -1446,7 +1452,9 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm
   }
   totals_finish<C, T, FWD>(a, a.partials_out + (size_t)q * C::M, L, sm);
   LBMZ_MARK(11);
-  if (wave < C::M && act) export_features<C, T>(a, q, f, x, v);
+  if constexpr (CTL) {
+    if (wave < C::M && act) export_features<C, T>(a, q, f, x, v);
+  }
 
   // S8, column half: inverse of the thresholded column, back to LDS.
   if (act) {
@@ -1473,9 +1481,9 @@ __device__ __forceinline__ void expand_any(const PatchArgs& a, int q, SM& sm, co
   else expand_columns_q<C, T, WAV, TOT, VF>(a, q, sm);
 }
 
-template <class C, class T, int WAV, bool FWD, int VF, class SM>
+template <class C, class T, int WAV, bool FWD, int VF, bool CTL, class SM>
 __device__ __forceinline__ bool compact_any(const PatchArgs& a, int q, SM& sm) {
-  if constexpr (VF == VF_F32) return column_compact<C, T, WAV, FWD>(a, q, sm);
+  if constexpr (VF == VF_F32) return column_compact<C, T, WAV, FWD, CTL>(a, q, sm);
   else return column_compact_q<C, T, WAV, FWD, VF>(a, q, sm);
 }
 
@@ -1511,7 +1519,7 @@ __device__ __forceinline__ void begin_patch(const PatchArgs& a, int q, SM& sm, L
 }
 
 // One step (time n -> n + 1) of patch q, S1..S9, after begin_patch and a barrier.
-template <class C, class T, int WAV, int SCH, int VF, class SM>
+template <class C, class T, int WAV, int SCH, int VF, bool CTL, class SM>
 __device__ __forceinline__ void step_one_patch(const PatchArgs& a, int q, SM& sm, const ListRegs<C, T>& lr) {
   LBMZ_MARK(0);
   LBMZ_MARK(14);
@@ -1527,7 +1535,7 @@ __device__ __forceinline__ void step_one_patch(const PatchArgs& a, int q, SM& sm
   row_pass<C, T, WAV, SCH, ROW_FWD>(a, q, sm.tile, sm.ghost);
   __syncthreads();
   LBMZ_MARK(4);
-  if (compact_any<C, T, WAV, true, VF>(a, q, sm)) {
+  if (compact_any<C, T, WAV, true, VF, CTL>(a, q, sm)) {
     LBMZ_MARK(5);
     export_rows<C, T, WAV, SCH>(a, q, sm.tile, sm.ghost);
     LBMZ_MARK(6);
@@ -1552,20 +1560,21 @@ __device__ __forceinline__ bool step_stops(const PatchArgs& a, bool reset_next, 
   return sm.misc[2] != 0u;
 }
 
-// One step of patch blockIdx.x (one workgroup per patch).
-template <class T, int P, int WAV, int SCH, int VF = VF_F32>
+// One step of patch blockIdx.x (one workgroup per patch).  CTL: per-patch
+// controls or network input export in use (float32 records only).
+template <class T, int P, int WAV, int SCH, int VF = VF_F32, bool CTL = false>
 __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(PatchArgs a) {
   using C = Cfg<T, P, WAV, SCH>;
   __shared__ Smem<C, T, VF> sm;
   ListRegs<C, T> lr;
   begin_patch<C, T, SCH, VF>(a, blockIdx.x, sm, lr);
   if (step_stops(a, blockIdx.x == 0, sm)) return;
-  step_one_patch<C, T, WAV, SCH, VF>(a, blockIdx.x, sm, lr);
+  step_one_patch<C, T, WAV, SCH, VF, CTL>(a, blockIdx.x, sm, lr);
 }
 
 // One step of every patch by a fixed set of resident workgroups that take
 // patches from a work queue (an atomic counter) until none is left.
-template <class T, int P, int WAV, int SCH, int VF = VF_F32>
+template <class T, int P, int WAV, int SCH, int VF = VF_F32, bool CTL = false>
 __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_persistent_kernel(PatchArgs a) {
   using C = Cfg<T, P, WAV, SCH>;
   __shared__ Smem<C, T, VF> sm;
@@ -1578,7 +1587,7 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_persiste
     ListRegs<C, T> lr;
     begin_patch<C, T, SCH, VF>(a, q, sm, lr);
     __syncthreads();
-    step_one_patch<C, T, WAV, SCH, VF>(a, q, sm, lr);
+    step_one_patch<C, T, WAV, SCH, VF, CTL>(a, q, sm, lr);
     __syncthreads();
   }
 }
@@ -1613,9 +1622,9 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
     if (a.mode == AUX_INIT) {
       row_pass<C, T, WAV, SCH, ROW_FWD>(a, q, sm.tile, sm.ghost);
       __syncthreads();
-      ok = compact_any<C, T, WAV, true, VF>(a, q, sm);
+      ok = compact_any<C, T, WAV, true, VF, true>(a, q, sm);
     } else {
-      ok = compact_any<C, T, WAV, false, VF>(a, q, sm);
+      ok = compact_any<C, T, WAV, false, VF, true>(a, q, sm);
     }
     if (!ok) return;
     export_rows<C, T, WAV, SCH>(a, q, sm.tile, sm.ghost);
@@ -1643,10 +1652,35 @@ constexpr size_t patch_lds_bytes() {
 // Operations of one compiled kernel family (see the dispatch of the runtime):
 // 0 step (one workgroup per patch), 1 auxiliary kernel, 2 LDS bytes,
 // 3 persistent step on `grid` workgroups, 4 / 5 the step / persistent kernel's
-// entry (for graph nodes), 6 threads per workgroup.
+// entry (for graph nodes), 6 threads per workgroup.  OP_CTL added to 0, 3, 4
+// or 5 selects the step kernels with per-patch controls (float32 records).
 template <class T, int P, int WAV, int SCH, int VF>
 size_t dispatch_op(int op, const PatchArgs* a, int grid, hipStream_t s, hipError_t* err) {
   using C = Cfg<T, P, WAV, SCH>;
+  if (op & OP_CTL) {
+    if constexpr (VF == VF_F32) {
+      switch (op & ~OP_CTL) {
+        case 0:
+          hipLaunchKernelGGL((patch_step_kernel<T, P, WAV, SCH, VF, true>), dim3(grid), dim3(C::NT), 0, s, *a);
+          *err = hipGetLastError();
+          return 0;
+        case 3:
+          hipLaunchKernelGGL((patch_step_persistent_kernel<T, P, WAV, SCH, VF, true>), dim3(grid), dim3(C::NT), 0,
+                             s, *a);
+          *err = hipGetLastError();
+          return 0;
+        case 4:
+          return reinterpret_cast<size_t>(reinterpret_cast<const void*>(&patch_step_kernel<T, P, WAV, SCH, VF, true>));
+        case 5:
+          return reinterpret_cast<size_t>(
+              reinterpret_cast<const void*>(&patch_step_persistent_kernel<T, P, WAV, SCH, VF, true>));
+        default:
+          break;
+      }
+    }
+    *err = hipErrorInvalidValue;
+    return 0;
+  }
   switch (op) {
     case 0:
       hipLaunchKernelGGL((patch_step_kernel<T, P, WAV, SCH, VF>), dim3(grid), dim3(C::NT), 0, s, *a);

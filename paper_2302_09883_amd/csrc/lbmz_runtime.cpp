@@ -48,15 +48,15 @@ static size_t dispatch_op_of(const KernelKey& k, int op, const PatchArgs* a, int
   return out;
 }
 
-hipError_t launch_step(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s) {
+hipError_t launch_step(const KernelKey& k, const PatchArgs& a, int npatch, hipStream_t s, bool ctl) {
   hipError_t e = hipSuccess;
-  dispatch_op_of(k, 0, &a, npatch, s, &e);
+  dispatch_op_of(k, ctl ? OP_CTL : 0, &a, npatch, s, &e);
   return e;
 }
 
-hipError_t launch_step_persistent(const KernelKey& k, const PatchArgs& a, int grid, hipStream_t s) {
+hipError_t launch_step_persistent(const KernelKey& k, const PatchArgs& a, int grid, hipStream_t s, bool ctl) {
   hipError_t e = hipSuccess;
-  dispatch_op_of(k, 3, &a, grid, s, &e);
+  dispatch_op_of(k, (ctl ? OP_CTL : 0) | 3, &a, grid, s, &e);
   return e;
 }
 
@@ -72,9 +72,9 @@ size_t kernel_lds_bytes(const KernelKey& k) {
   return e == hipSuccess ? v : 0;
 }
 
-const void* step_kernel_entry(const KernelKey& k, bool persistent) {
+const void* step_kernel_entry(const KernelKey& k, bool persistent, bool ctl) {
   hipError_t e = hipSuccess;
-  const size_t v = dispatch_op_of(k, persistent ? 5 : 4, nullptr, 0, nullptr, &e);
+  const size_t v = dispatch_op_of(k, (ctl ? OP_CTL : 0) | (persistent ? 5 : 4), nullptr, 0, nullptr, &e);
   return e == hipSuccess ? reinterpret_cast<const void*>(v) : nullptr;
 }
 
@@ -110,7 +110,7 @@ struct lbmz_ctx {
   hipGraph_t graph[2] = {nullptr, nullptr};      // GRAPH_STEPS launches from buffer parity 0 / 1
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipGraphNode_t gnode[2][6] = {};
-  int graph_mode[2] = {-1, -1};                  // exec_persistent at instantiation
+  int graph_mode[2] = {-1, -1};                  // exec_mode() at instantiation
   PatchArgs gargs[6] = {};
   double* eps_patch = nullptr;   // per-patch thresholds (device), or null
   int8_t* lev_patch = nullptr;   // per-patch threshold level counts (device), or null
@@ -486,6 +486,14 @@ void drop_graphs(lbmz_ctx* c) {
   }
 }
 
+// The step kernel with per-patch controls runs when any of them is set.
+bool uses_controls(const lbmz_ctx* c) {
+  return c->dim == 2 && (c->eps_patch || c->lev_patch || c->features);
+}
+
+// Graph mode of the current launches: persistent or not, with controls or not.
+int exec_mode(const lbmz_ctx* c) { return c->exec_persistent + 2 * (uses_controls(c) ? 1 : 0); }
+
 int step_grid(lbmz_ctx* c) {
   if (c->dim == 3) return c->slots3;   // the 3-D step kernel is always persistent
   return c->exec_persistent ? c->persist_grid : c->npatch;
@@ -501,7 +509,7 @@ void chunk_args(lbmz_ctx* c, int par, unsigned e0) {
 
 hipKernelNodeParams node_params(lbmz_ctx* c, int i, void** slot) {
   hipKernelNodeParams p{};
-  p.func = const_cast<void*>(step_kernel_entry(c->key, c->exec_persistent != 0));
+  p.func = const_cast<void*>(step_kernel_entry(c->key, c->exec_persistent != 0, uses_controls(c)));
   p.gridDim = dim3((unsigned)step_grid(c));
   p.blockDim = dim3((unsigned)kernel_threads(c->key));
   p.sharedMemBytes = 0;
@@ -515,7 +523,7 @@ hipKernelNodeParams node_params(lbmz_ctx* c, int i, void** slot) {
 int launch_chunk(lbmz_ctx* c, int par, unsigned e0) {
   chunk_args(c, par, e0);
   void* slots[GRAPH_STEPS][1];
-  if (!c->gexec[par] || c->graph_mode[par] != c->exec_persistent) {
+  if (!c->gexec[par] || c->graph_mode[par] != exec_mode(c)) {
     if (c->gexec[par]) (void)hipGraphExecDestroy(c->gexec[par]);
     if (c->graph[par]) (void)hipGraphDestroy(c->graph[par]);
     c->gexec[par] = nullptr;
@@ -528,7 +536,7 @@ int launch_chunk(lbmz_ctx* c, int par, unsigned e0) {
       HIPCHK(c, hipGraphAddKernelNode(&c->gnode[par][i], c->graph[par], dep, i ? 1 : 0, &p));
     }
     HIPCHK(c, hipGraphInstantiate(&c->gexec[par], c->graph[par], nullptr, nullptr, 0));
-    c->graph_mode[par] = c->exec_persistent;
+    c->graph_mode[par] = exec_mode(c);
   } else {
     for (int i = 0; i < GRAPH_STEPS; ++i) {
       hipKernelNodeParams p = node_params(c, i, slots[i]);
@@ -541,8 +549,9 @@ int launch_chunk(lbmz_ctx* c, int par, unsigned e0) {
 
 int launch_one(lbmz_ctx* c, int in, unsigned e) {
   PatchArgs a = args_for(c, in, in ^ 1, e);
-  if (c->exec_persistent) HIPCHK(c, launch_step_persistent(c->key, a, step_grid(c), c->stream));
-  else HIPCHK(c, launch_step(c->key, a, step_grid(c), c->stream));
+  const bool ctl = uses_controls(c);
+  if (c->exec_persistent) HIPCHK(c, launch_step_persistent(c->key, a, step_grid(c), c->stream, ctl));
+  else HIPCHK(c, launch_step(c->key, a, step_grid(c), c->stream, ctl));
   return LBMZ_OK;
 }
 
@@ -615,7 +624,7 @@ int lbmz_create(const lbmz_grid* grid, const lbmz_scheme* scheme, const lbmz_pat
   }
   if (rc == LBMZ_OK && c->dim == 3) {
     int ncu = 0, per_cu = 0;
-    const void* fn = step_kernel_entry(c->key, true);
+    const void* fn = step_kernel_entry(c->key, true, false);
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || !fn ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kernel_threads(c->key), 0) != hipSuccess)
       rc = fail(c, LBMZ_EDEVICE, "cannot size the 3-D step grid");
@@ -1256,7 +1265,7 @@ int lbmz_set_execution(lbmz_ctx* c, int persistent, int graph) {
   if (persistent && c->persist_grid <= 0) {
     int ncu = 0, per_cu = 0;
     HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
-    const void* fn = step_kernel_entry(c->key, true);
+    const void* fn = step_kernel_entry(c->key, true, false);
     if (!fn) return fail(c, LBMZ_EINVAL, "no persistent kernel for this configuration");
     HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kernel_threads(c->key), 0));
     c->persist_grid = std::max(1, std::min(c->npatch, ncu * std::max(1, per_cu)));
