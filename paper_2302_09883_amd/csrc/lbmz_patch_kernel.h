@@ -1099,6 +1099,79 @@ __device__ __forceinline__ void prefetch_lists(const PatchArgs& a, int q, ListRe
   }
 }
 
+// Mask words of a bitmask record, word k in lane k of w0 (k < 64) or lane
+// k - 64 of w1.
+template <class C, class T>
+__device__ __forceinline__ void load_mask_words(const uint8_t* rec, uint32_t nnz, int lane, unsigned long long& w0,
+                                                unsigned long long& w1) {
+  const unsigned long long* words =
+      reinterpret_cast<const unsigned long long*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
+  w0 = lane < C::W ? words[lane] : 0ull;
+  w1 = (64 + lane) < C::W ? words[64 + lane] : 0ull;
+}
+
+// One value of a record through a buffer resource: byte offset voff (per
+// lane) + soff (uniform).  Reads outside the record return 0.
+template <class T>
+__device__ __forceinline__ T record_value(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float record_value<float>(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double record_value<double>(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+}
+
+// Column x = lane of a bitmask record (values at rec, nnz of them; mask
+// words in w0 / w1): node (x, y) of an owned row sits in word y / RPW at bit
+// x + P (y % RPW), the shared row y = P in the rim words (see rim_join); its
+// value is the one after the kept nodes before that bit.  The word of a row
+// is wave-uniform (scalar registers; the values before it by scalar adds),
+// the lane's rank inside it is one mbcnt, and the value comes through a
+// buffer load with that rank as its only per-lane offset.  A lane whose bit
+// is clear loads from an offset outside the record and so receives 0.
+template <class C, class T>
+__device__ __forceinline__ void gather_owned(const uint8_t* rec, uint32_t nnz, unsigned long long w0,
+                                             unsigned long long w1, T* v) {
+  constexpr unsigned long long LANES = (C::P == 64) ? ~0ull : ((1ull << C::P) - 1ull);
+  constexpr uint32_t B = sizeof(T);
+  constexpr uint32_t OUTSIDE = 0x80000000u;   // beyond any record (at most 64 KB)
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(rec), 0, (int)(nnz * B), 0x00020000);
+  auto word = [&](int k) { return k < 64 ? readlane64(w0, k) : readlane64(w1, k - 64); };
+  uint32_t pk = 0u;   // values before the current word
+  unsigned long long wk = 0ull;
+#pragma unroll
+  for (int y = 0; y < C::P; ++y) {
+    const int r = y % C::RPW;
+    if (r == 0) {
+      if (y > 0) pk += (uint32_t)__popcll(wk);
+      wk = word(y / C::RPW);
+    }
+    const unsigned long long sh = (wk >> (C::P * r)) & LANES;
+    const uint32_t base = pk + (r ? (uint32_t)__popcll(wk & ((1ull << (C::P * r)) - 1ull)) : 0u);
+    const uint32_t k = __builtin_amdgcn_mbcnt_hi((uint32_t)(sh >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)sh, 0u));
+    v[y] = record_value<T>(rs, __builtin_amdgcn_inverse_ballot_w64(sh) ? k * B : OUTSIDE, base * B);
+  }
+  if constexpr (C::RIM) {
+    pk += (uint32_t)__popcll(wk);   // the owned block's values
+    unsigned long long sh;
+    uint32_t base;
+    if constexpr (C::P == 64) {
+      // word CW: the shared column; word CW + 1: the shared row
+      base = pk + (uint32_t)__popcll(word(C::CW));
+      sh = word(C::CW + 1);
+    } else {
+      const unsigned long long r0 = word(C::CW);
+      base = pk + (uint32_t)__popcll(r0 & ((1ull << C::P) - 1ull));
+      sh = (r0 >> C::P) & LANES;
+    }
+    const uint32_t k = __builtin_amdgcn_mbcnt_hi((uint32_t)(sh >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)sh, 0u));
+    v[C::P] = record_value<T>(rs, __builtin_amdgcn_inverse_ballot_w64(sh) ? k * B : OUTSIDE, base * B);
+  }
+}
+
 template <class C, class T, int WAV, bool TOT, bool PREZ, class SM>
 __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm, const ListRegs<C, T>& lr) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
@@ -1132,33 +1205,13 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
     if (w & MASK_BIT) {
       const uint32_t nnz = w & ~MASK_BIT;
       const uint8_t* rec = pool + 16ull * te(2 * f);
-      const T* vals = reinterpret_cast<const T*>(rec);
-      const unsigned long long* words =
-          reinterpret_cast<const unsigned long long*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
-      const unsigned long long w0 = lane < C::W ? words[lane] : 0ull;
-      const unsigned long long w1 = (64 + lane) < C::W ? words[64 + lane] : 0ull;
-      const int c0 = __popcll(w0);
-      const int c1 = __popcll(w1);
-      const int i0 = wave_incl_scan(c0);
-      const int tot0 = __shfl(i0, 63, 64);
-      const int i1 = wave_incl_scan(c1);
-      const int p0 = i0 - c0;
-      const int p1 = tot0 + i1 - c1;
-      const int x = lane;
-      const bool act = x < C::P;
+      unsigned long long w0, w1;
+      load_mask_words<C, T>(rec, nnz, lane, w0, w1);
       T v[C::S];
-#pragma unroll
-      for (int y = 0; y < C::S; ++y) {
-        // word and bit of node (x, y): owned rows first, then the shared row
-        const int kw = (y < C::P) ? y / C::RPW : ((C::P == 64) ? C::CW + 1 : C::CW);
-        const int b = (y < C::P) ? x + C::P * (y % C::RPW) : ((C::P == 64) ? x : C::P + x);
-        const unsigned long long wk = kw < 64 ? readlane64(w0, kw) : readlane64(w1, kw - 64);
-        const int pk = kw < 64 ? __builtin_amdgcn_readlane(p0, kw) : __builtin_amdgcn_readlane(p1, kw - 64);
-        v[y] = T(0);
-        if (act && ((wk >> b) & 1ull)) v[y] = vals[pk + __popcll(wk & below(b))];
-      }
+      gather_owned<C, T>(rec, nnz, w0, w1, v);
+      const int x = lane;
       double part = 0.0;
-      if (act) {
+      if (x < C::P) {
         if constexpr (TOT) part = column_sample_sum<C, T>(v, x, L);
         LF::inv(v, L);
         store_col<C>(v, sm.tile, field_base<C>(f), x);
@@ -1240,6 +1293,73 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
     }
     __syncthreads();
   }
+}
+
+// Lane `lane` (wave-uniform) of `old` replaced by the wave-uniform value u
+// (v_writelane with the lane in M0: it reads at most one other scalar).
+__device__ __forceinline__ uint32_t write_lane(uint32_t old, uint32_t u, int lane) {
+  asm("s_mov_b32 m0, %2\n\ts_nop 0\n\tv_writelane_b32 %0, %1, m0" : "+v"(old) : "s"(u), "s"(lane) : "m0");
+  return old;
+}
+
+// One value (or index-list entry) into a record through a buffer resource;
+// a store at an offset outside the resource writes nothing.
+template <class T>
+__device__ __forceinline__ void record_store(T v, __amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ void record_store<float>(float v, __amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, (int)voff, (int)soff, 0);
+}
+template <>
+__device__ __forceinline__ void record_store<double>(double v, __amdgpu_buffer_rsrc_t rs, uint32_t voff,
+                                                     uint32_t soff) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, (int)voff, (int)soff, 0);
+}
+
+// Stores of the owned rows of a column-pass line (S7): the rank of a kept
+// coefficient is the count of kept ones before it in record order; in a row,
+// the kept lanes below it (one mbcnt of the row's ballot).  Lanes with
+// nothing to store take an offset outside the record.  Bitmask records (MASK)
+// collect the row ballots into mask words, word y / RPW in lane y / RPW of
+// myw; index-list records store the node index of each value.  Returns the
+// count of kept owned coefficients.
+template <class C, class T, bool MASK>
+__device__ __forceinline__ int store_owned_rows(const T* v, unsigned long long actm, uint8_t* rec,
+                                                uint32_t nnz, uint32_t vb, unsigned long long& myw) {
+  constexpr uint32_t B = sizeof(T);
+  constexpr uint32_t OUTSIDE = 0x80000000u;   // beyond any record (at most 64 KB)
+  const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(rec, 0, (int)(nnz * B), 0x00020000);
+  const __amdgpu_buffer_rsrc_t ri =
+      __builtin_amdgcn_make_buffer_rsrc(rec + vb, 0, MASK ? 0 : (int)(2u * nnz), 0x00020000);
+  const int x = lane_id();
+  int run = 0;
+  unsigned long long wd = 0ull;
+  uint32_t wlo = 0u, whi = 0u;
+#pragma unroll
+  for (int y = 0; y < C::P; ++y) {
+    const unsigned long long b = __ballot(v[y] != T(0)) & actm;   // lanes without a line hold zeros
+    if (b != 0ull) {
+      const uint32_t k = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+      const bool kept = __builtin_amdgcn_inverse_ballot_w64(b);
+      record_store<T>(v[y], rv, kept ? k * B : OUTSIDE, (uint32_t)run * B);
+      if constexpr (!MASK)
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(x + C::P * y), ri, (int)(kept ? 2u * k : OUTSIDE),
+                                              2 * run, 0);
+      run += __popcll(b);
+    }
+    if constexpr (MASK) {
+      // mask word y / RPW collects RPW rows; lane y / RPW keeps it
+      wd |= b << (C::P * (y % C::RPW));
+      if (y % C::RPW == C::RPW - 1) {
+        wlo = write_lane(wlo, (uint32_t)wd, y / C::RPW);
+        whi = write_lane(whi, (uint32_t)(wd >> 32), y / C::RPW);
+        wd = 0ull;
+      }
+    }
+  }
+  myw = ((unsigned long long)whi << 32) | wlo;
+  return run;
 }
 
 // ---------------------------------------------------------------------------
@@ -1377,34 +1497,17 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm
   // it in record order (owned rows, shared column, shared row, corner); in a
   // row, the kept lanes below it (mbcnt).
   if (wave < C::M) {
-    uint8_t* rec = a.pool_out + 16ull * (base16 + sm.rel16[f]);
+    // wave-uniform record geometry (scalar registers)
+    auto uni = [](uint32_t u) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)u); };
+    uint8_t* rec = a.pool_out + 16ull * uni(base16 + sm.rel16[f]);
     T* vals = reinterpret_cast<T*>(rec);
-    const bool ismask = sm.ismask[f] != 0u;
-    uint16_t* idx = reinterpret_cast<uint16_t*>(rec + sm.vb[f]);
+    const bool ismask = uni(sm.ismask[f]) != 0u;
+    const uint32_t nnz = uni(sm.nnz[f]);
+    const uint32_t vb = uni(sm.vb[f]);
+    uint16_t* idx = reinterpret_cast<uint16_t*>(rec + vb);
     unsigned long long myw = 0ull;
-    unsigned long long wd = 0ull;
-    int run = 0;
-#pragma unroll
-    for (int y = 0; y < C::P; ++y) {
-      const unsigned long long b = __ballot(v[y] != T(0)) & actm;
-      if (b != 0ull) {
-        if (act && v[y] != T(0)) {
-          const int rank = run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
-          vals[rank] = v[y];
-          if (!ismask) idx[rank] = (uint16_t)(x + C::P * y);
-        }
-        run += __popcll(b);
-      }
-      if (ismask) {
-        // mask word y / RPW collects RPW rows; lane y / RPW keeps it
-        wd |= b << (C::P * (y % C::RPW));
-        if (y % C::RPW == C::RPW - 1) {
-          if (lane == y / C::RPW) myw = wd;
-          wd = 0ull;
-        }
-      }
-    }
+    const int run = ismask ? store_owned_rows<C, T, true>(v, actm, rec, nnz, vb, myw)
+                           : store_owned_rows<C, T, false>(v, actm, rec, nnz, vb, myw);
     if constexpr (C::RIM) {
       const unsigned long long col = sm.colbits[f];
       const unsigned long long rowb = sm.rowbits[f];
@@ -1431,7 +1534,7 @@ __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm
         if (!ismask) idx[rank] = (uint16_t)(C::P * C::P + 2 * C::P);
       }
     }
-    if (ismask && lane < C::CW) reinterpret_cast<unsigned long long*>(rec + sm.vb[f])[lane] = myw;
+    if (ismask && lane < C::CW) reinterpret_cast<unsigned long long*>(rec + vb)[lane] = myw;
   }
   if (tid < C::M) {
     const int g = tid;
