@@ -65,8 +65,9 @@ struct TileLayout {
   static constexpr int total() { return start(M); }
 };
 
-template <class T, int P_, int WAV, int SCH>
+template <class T, int P_, int WAV, int SCH, bool PERS = false>
 struct Cfg {
+  static constexpr bool PERSISTENT = PERS;                  // code of the persistent kernel's loop
   static constexpr int P = P_;
   static constexpr bool RIM = (WAV == W_BL53);              // tiles carry the shared line P
   static constexpr int S = RIM ? P + 1 : P;                 // tile nodes per side
@@ -127,7 +128,7 @@ struct Smem {
   uint32_t vb[C::M];
   uint32_t rb[C::M];
   uint32_t te[2 * C::M];                 // offset-table entries of the patch being expanded
-  unsigned misc[4];
+  unsigned misc[5];                      // pool status, allocation base, stop flag, queue slots
   typename std::conditional<VF == VF_F32, NoLds, NarrowLds<C>>::type nq;
 };
 
@@ -137,6 +138,25 @@ struct Smem {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// Work-item id as the patch code of configuration C sees it.  In the
+// persistent kernel it is opaque to the optimiser: values derived from it
+// are recomputed where they are used instead of being hoisted out of the
+// patch loop and held in registers across it.
+template <class C>
+__device__ __forceinline__ unsigned tid_of() {
+  unsigned t = threadIdx.x;
+  if constexpr (C::PERSISTENT) asm volatile("" : "+v"(t));
+  return t;
+}
+template <class C>
+__device__ __forceinline__ int lane_of() {
+  return (int)(tid_of<C>() & 63u);
+}
+template <class C>
+__device__ __forceinline__ int wave_of() {
+  return __builtin_amdgcn_readfirstlane((int)(tid_of<C>() >> 6));
+}
 
 __device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
@@ -360,8 +380,8 @@ struct Lift {
 // in column passes, a row y in row passes).
 template <class C>
 __device__ __forceinline__ bool pass_line(int& f, int& r) {
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
+  const int wave = tid_of<C>() >> 6;
+  const int lane = tid_of<C>() & 63;
   if (wave < C::M) {
     f = wave;
     r = lane;
@@ -572,8 +592,8 @@ __device__ __forceinline__ double column_sample_sum(const T* v, int x, int L) {
 // shared-column wave stores one partial per lane (field) in sm.totface.
 template <class C, class T, class SM>
 __device__ __forceinline__ void totals_partial(double part, SM& sm) {
-  const int wave = threadIdx.x >> 6;
-  const int lane = lane_id();
+  const int wave = tid_of<C>() >> 6;
+  const int lane = lane_of<C>();
   if (wave < C::M) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
@@ -595,7 +615,7 @@ __device__ __forceinline__ void totals_partial(double part, SM& sm) {
 // hence its field's total, non-finite.
 template <class C, class T, bool CHECK, class SM>
 __device__ __forceinline__ void totals_finish(const PatchArgs& a, double* out, int L, SM& sm) {
-  const int tid = threadIdx.x;
+  const int tid = tid_of<C>();
   if (tid < C::M) {
     const double s = (double)(1 << L) * (double)(1 << L);
     const double t = s * (sm.tot[tid] + (C::RIM ? sm.totface[tid] : 0.0));
@@ -647,7 +667,7 @@ __device__ __forceinline__ T* gather_lbm_at(const PatchArgs& a, int q, int k, T*
 
 template <class C, class T>
 __device__ __forceinline__ void gather_lbm(const PatchArgs& a, int q, T* tile, T* ghost) {
-  for (int k = threadIdx.x; k < 4 * 3 * C::S; k += C::NT) {
+  for (int k = tid_of<C>(); k < 4 * 3 * C::S; k += C::NT) {
     T v;
     T* d = gather_lbm_at<C, T>(a, q, k, tile, ghost, v);
     *d = v;
@@ -660,7 +680,7 @@ __device__ __forceinline__ void gather_fv(const PatchArgs& a, int q, T* ghost) {
   const T* h = static_cast<const T*>(a.halo_in);
   const int px = q % a.npx;
   const int py = q / a.npx;
-  for (int k = threadIdx.x; k < 4 * C::NSLOT * C::S; k += C::NT) {
+  for (int k = tid_of<C>(); k < 4 * C::NSLOT * C::S; k += C::NT) {
     const int side = k / (C::NSLOT * C::S);
     const int rem = k - side * (C::NSLOT * C::S);
     const int slot = rem / C::S;
@@ -805,9 +825,9 @@ __device__ __forceinline__ void export_rows_bl53(const PatchArgs& a, int q, cons
       h[((hq + 0) * C::NSLOT + f) * C::S + y] = bl53_inv_edge<C, T, true>(row, L);
       h[((hq + 1) * C::NSLOT + f) * C::S + y] = bl53_inv_edge<C, T, false>(row, L);
     }
-  } else if ((int)(threadIdx.x >> 6) >= C::NPASS) {
+  } else if ((int)(tid_of<C>() >> 6) >= C::NPASS) {
     // helper item: field g, row HI (even item) or LO (odd item)
-    const int ht = (int)threadIdx.x - 64 * C::NPASS;
+    const int ht = (int)tid_of<C>() - 64 * C::NPASS;
     const int g = ht >> 1;
     if (g < C::M) {
       const bool hi = (ht & 1) == 0;
@@ -867,7 +887,7 @@ __device__ __forceinline__ void stencil_lbm(const PatchArgs& a, T* tile) {
   T res[C::NPER][9];
 #pragma unroll
   for (int k = 0; k < C::NPER; ++k) {
-    const int t = threadIdx.x + k * C::NT;
+    const int t = tid_of<C>() + k * C::NT;
     if (t < C::NC) {
       const int y = t / C::S;
       const int base = y * C::RS + (t - y * C::S);
@@ -880,7 +900,7 @@ __device__ __forceinline__ void stencil_lbm(const PatchArgs& a, T* tile) {
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < C::NPER; ++k) {
-    const int t = threadIdx.x + k * C::NT;
+    const int t = tid_of<C>() + k * C::NT;
     if (t < C::NC) {
       const int y = t / C::S;
       const int base = y * C::RS + (t - y * C::S);
@@ -906,7 +926,7 @@ __device__ __forceinline__ void stencil_fv(const PatchArgs& a, T* tile, const T*
     const T* g = ghost + f * C::S;
 #pragma unroll
     for (int k = 0; k < C::NPER; ++k) {
-      const int t = threadIdx.x + k * C::NT;
+      const int t = tid_of<C>() + k * C::NT;
       if (t < C::NC) {
         const int y = t / C::S;
         const int x = t - y * C::S;
@@ -929,7 +949,7 @@ __device__ __forceinline__ void stencil_fv(const PatchArgs& a, T* tile, const T*
   for (int f = 0; f < C::M; ++f) {
 #pragma unroll
     for (int k = 0; k < C::NPER; ++k) {
-      const int t = threadIdx.x + k * C::NT;
+      const int t = tid_of<C>() + k * C::NT;
       if (t < C::NC) {
         const int y = t / C::S;
         tile[C::Lay::fb(f) + y * C::RS + (t - y * C::S)] = res[f][k];
@@ -989,7 +1009,7 @@ __device__ __forceinline__ void stencil_euler(const PatchArgs& a, T* tile, const
   T res[4][C::NPER];
 #pragma unroll
   for (int k = 0; k < C::NPER; ++k) {
-    const int t = threadIdx.x + k * C::NT;
+    const int t = tid_of<C>() + k * C::NT;
     if (t < C::NC) {
       const int y = t / C::S;
       const int x = t - y * C::S;
@@ -1015,7 +1035,7 @@ __device__ __forceinline__ void stencil_euler(const PatchArgs& a, T* tile, const
   for (int f = 0; f < 4; ++f) {
 #pragma unroll
     for (int k = 0; k < C::NPER; ++k) {
-      const int t = threadIdx.x + k * C::NT;
+      const int t = tid_of<C>() + k * C::NT;
       if (t < C::NC) {
         const int y = t / C::S;
         tile[C::Lay::fb(f) + y * C::RS + (t - y * C::S)] = res[f][k];
@@ -1045,7 +1065,7 @@ static __device__ unsigned long long lbmz_phase_clock[4096 * 16];
 // next barrier); issued early so that their latency overlaps other loads.
 template <class C, class SM>
 __device__ __forceinline__ void prefetch_table(const PatchArgs& a, int q, SM& sm) {
-  if (threadIdx.x < 2 * C::M) sm.te[threadIdx.x] = a.table_in[2 * (size_t)q * C::M + threadIdx.x];
+  if (tid_of<C>() < 2 * C::M) sm.te[tid_of<C>()] = a.table_in[2 * (size_t)q * C::M + tid_of<C>()];
 }
 
 // ---------------------------------------------------------------------------
@@ -1071,13 +1091,17 @@ struct ListRegs {
 // that precedes the expansion).
 template <class C, class T>
 __device__ __forceinline__ void prefetch_lists(const PatchArgs& a, int q, ListRegs<C, T>& lr) {
-  const int wave = wave_id();
+  const int wave = wave_of<C>();
   if (wave < C::NPASS) return;
-  const int ht = threadIdx.x - 64 * C::NPASS;
+  const int ht = tid_of<C>() - 64 * C::NPASS;
   const uint32_t* tq = a.table_in + 2 * (size_t)q * C::M;
+  // all table entries first (one round trip), then every field's loads
+  uint32_t tw[2 * C::M];
+#pragma unroll
+  for (int i = 0; i < 2 * C::M; ++i) tw[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)tq[i]);
 #pragma unroll
   for (int f = 0; f < C::M; ++f) {
-    const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)tq[2 * f + 1]);
+    const uint32_t w = tw[2 * f + 1];
     const uint32_t nnz = w & ~MASK_BIT;
 #pragma unroll
     for (int u = 0; u < C::LPT; ++u) {
@@ -1085,7 +1109,7 @@ __device__ __forceinline__ void prefetch_lists(const PatchArgs& a, int q, ListRe
       lr.lv[f][u] = T(0);
     }
     if (!(w & MASK_BIT)) {
-      const uint8_t* rec = a.pool_in + 16ull * (uint32_t)__builtin_amdgcn_readfirstlane((int)tq[2 * f]);
+      const uint8_t* rec = a.pool_in + 16ull * tw[2 * f];
       const uint16_t* idx = reinterpret_cast<const uint16_t*>(rec + ((nnz * (uint32_t)sizeof(T) + 7u) & ~7u));
 #pragma unroll
       for (int u = 0; u < C::LPT; ++u) {
@@ -1175,9 +1199,9 @@ __device__ __forceinline__ void gather_owned(const uint8_t* rec, uint32_t nnz, u
 template <class C, class T, int WAV, bool TOT, bool PREZ, class SM>
 __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm, const ListRegs<C, T>& lr) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wave = wave_id();
+  const int tid = tid_of<C>();
+  const int lane = lane_of<C>();
+  const int wave = wave_of<C>();
   const int L = a.levels;
   // offset-table entries, loaded into LDS by prefetch_table before the last barrier
   // te: wave-uniform index (one scalar value), tel: index that varies over the lanes
@@ -1332,7 +1356,7 @@ __device__ __forceinline__ int store_owned_rows(const T* v, unsigned long long a
   const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(rec, 0, (int)(nnz * B), 0x00020000);
   const __amdgpu_buffer_rsrc_t ri =
       __builtin_amdgcn_make_buffer_rsrc(rec + vb, 0, MASK ? 0 : (int)(2u * nnz), 0x00020000);
-  const int x = lane_id();
+  const int x = lane_of<C>();
   int run = 0;
   unsigned long long wd = 0ull;
   uint32_t wlo = 0u, whi = 0u;
@@ -1374,9 +1398,9 @@ template <class C, class T, int WAV, bool FWD, bool CTL, class SM>
 __device__ __forceinline__ bool column_compact(const PatchArgs& a, int q, SM& sm) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
   static_assert(sizeof(sm.ghost) >= sizeof(T) * C::M * C::S, "shared-column staging does not fit");
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wave = wave_id();
+  const int tid = tid_of<C>();
+  const int lane = lane_of<C>();
+  const int wave = wave_of<C>();
   const int L = a.levels;
   int f, x;
   const bool act = pass_line<C>(f, x);
@@ -1604,7 +1628,7 @@ __device__ __forceinline__ void begin_patch(const PatchArgs& a, int q, SM& sm, L
     // the ghost rows outside them are not touched); then the loaded values
     // go to LDS.
     static_assert(4 * 3 * C::S <= C::NT, "one ghost value per thread");
-    const int tid = threadIdx.x;
+    const int tid = tid_of<C>();
     T gv = T(0);
     T* gd = nullptr;
     if (tid < 4 * 3 * C::S) gd = gather_lbm_at<C, T>(a, q, tid, sm.tile, sm.ghost, gv);
@@ -1675,22 +1699,37 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_kernel(P
   step_one_patch<C, T, WAV, SCH, VF, CTL>(a, blockIdx.x, sm, lr);
 }
 
+// The kernel arguments as a reference into the kernel-argument segment that
+// the compiler cannot hoist out of a loop: the persistent kernel re-reads
+// them (scalar loads) for every patch instead of holding them in registers
+// across the whole loop.
+__device__ __forceinline__ const PatchArgs& patch_args_reread() {
+  auto kp = __builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(kp));
+  return *(const PatchArgs*)kp;
+}
+
 // One step of every patch by a fixed set of resident workgroups that take
 // patches from a work queue (an atomic counter) until none is left.
 template <class T, int P, int WAV, int SCH, int VF = VF_F32, bool CTL = false>
 __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_step_persistent_kernel(PatchArgs a) {
-  using C = Cfg<T, P, WAV, SCH>;
+  using C = Cfg<T, P, WAV, SCH, true>;
   __shared__ Smem<C, T, VF> sm;
   if (step_stops(a, blockIdx.x == 0, sm)) return;
-  for (;;) {
-    if (threadIdx.x == 0) sm.misc[3] = atomicAdd(&a.ctrl->queue[a.epoch % 3u], 1u);
-    __syncthreads();
-    const int q = (int)sm.misc[3];
-    if (q >= a.npatch) break;
+  if (threadIdx.x == 0) sm.misc[3] = atomicAdd(&a.ctrl->queue[a.epoch % 3u], 1u);
+  __syncthreads();
+  for (unsigned it = 0;; ++it) {
+    // patch indices alternate between two LDS slots: the next one is taken
+    // while this patch's loads are in flight, by the last wave (no line in
+    // the passes), into the slot that no wave reads during this patch
+    const int q = __builtin_amdgcn_readfirstlane((int)sm.misc[3 + (it & 1u)]);   // uniform: scalar addressing
+    if (q >= a.npatch) break;   // every wave reads the same q and leaves together
+    const PatchArgs& ap = patch_args_reread();
     ListRegs<C, T> lr;
-    begin_patch<C, T, SCH, VF>(a, q, sm, lr);
+    begin_patch<C, T, SCH, VF>(ap, q, sm, lr);
+    if (threadIdx.x == C::NT - 64) sm.misc[3 + ((it + 1u) & 1u)] = atomicAdd(&ap.ctrl->queue[ap.epoch % 3u], 1u);
     __syncthreads();
-    step_one_patch<C, T, WAV, SCH, VF, CTL>(a, q, sm, lr);
+    step_one_patch<C, T, WAV, SCH, VF, CTL>(ap, q, sm, lr);
     __syncthreads();
   }
 }

@@ -140,9 +140,9 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
   static_assert(sizeof(T) == 4, "narrow formats store float32 coefficients");
   static_assert(sizeof(sm.ghost) >= sizeof(T) * C::M * C::S, "shared-column staging does not fit");
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wave = wave_id();
+  const int tid = tid_of<C>();
+  const int lane = lane_of<C>();
+  const int wave = wave_of<C>();
   const int L = a.levels;
   const int L1 = L + 1;
   const int lmask = (1 << L) - 1;
@@ -464,9 +464,9 @@ __device__ __forceinline__ bool column_compact_q(const PatchArgs& a, int q, SM& 
 template <class C, class T, int WAV, bool TOT, int VF, class SM>
 __device__ __forceinline__ void expand_columns_q(const PatchArgs& a, int q, SM& sm) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wave = wave_id();
+  const int tid = tid_of<C>();
+  const int lane = lane_of<C>();
+  const int wave = wave_of<C>();
   const int L = a.levels;
   const int L1 = L + 1;
   const int SC = ((C::S - 1) >> L) + 1;
