@@ -773,10 +773,10 @@ __global__ __launch_bounds__(1024) void d3q19_step_kernel(PatchArgs a) {
   for (;;) {
     if (threadIdx.x == 0) sm.misc[3] = atomicAdd(&a.ctrl->queue[a.epoch % 3u], 1u);
     __syncthreads();
-    const int q = (int)sm.misc[3];
+    const int q = __builtin_amdgcn_readfirstlane((int)sm.misc[3]);   // uniform: scalar addressing
     __syncthreads();
     if (q >= a.npatch) break;
-    step_patch<C>(a, q, scr, sm);
+    step_patch<C>(patch_args_reread(), q, scr, sm);
   }
 }
 
