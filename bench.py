@@ -376,6 +376,19 @@ def cpu_baseline(steps: int = 3, workers: int | None = None, n: int = N):
             "cpu": info}
 
 
+def copy_calibration():
+    """Three plain device copies of 256 MiB: the kernel of known traffic that
+    the HBM byte counters are scaled by."""
+    import torch
+
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def hbm_point(n: int, steps: int, warmup: int = 5):
     """The operating point bound by HBM bytes: eps = 0 keeps every coefficient
     (bitmask records, stored density ~0.96).  Plain launches, no error run.
@@ -419,6 +432,9 @@ def main():
                     help="skip the eps=0 runs at 2048^2 and 4096^2 (the HBM-bound operating points)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (the reference kernel for counter scaling)")
+    ap.add_argument("--hbm-point", type=int, default=0, metavar="N",
+                    help="profiling aid: run only the eps=0 operating point on an N x N grid for --steps steps "
+                         "and print its figures (no bench line)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -426,6 +442,15 @@ def main():
         print("bench.py measures one GPU: the compressed patch loop runs on a single MI355X "
               "(multi-GPU sharding is a design note only); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.hbm_point:
+        import torch
+
+        torch.cuda.set_device(0)
+        if args.copy_calibration:
+            copy_calibration()
+        print(json.dumps(hbm_point(args.hbm_point, args.steps, args.warmup)), flush=True)
+        return
 
     # the CPU leg first: its worker processes are forked before the GPU is touched
     cpu = None
@@ -476,12 +501,7 @@ def main():
         print(f"[bench] patch-shape tuner: {shape['chosen']}", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
 
     hbm_points = None
     if not args.no_hbm_points:
