@@ -42,9 +42,12 @@ reasons in the design notes of the repository):
   transform has rank ``r = L - lev`` (0 = coarsest detail); capped threshold
   ``eps * 2**max(r_x, r_y)``, accumulation ``eps * 2**(r_x + r_y)``, constant
   ``eps``; a coefficient is a detail if it is a detail in at least one
-  dimension, and a sample dimension contributes rank 0.  Parity unpinned for
-  the capped and accumulation rules (the paper only shows them in figures);
-  the constant rule is pinned by the worked example of Section 2.1.2.
+  dimension, and a sample dimension contributes rank 0.  The direction of
+  the rank is pinned by the paper's own comparison of the rules (capped
+  keeps fewer coefficients than constant at the same error; the opposite
+  direction fails it); the values of the capped and accumulation thresholds
+  have no printed example (the paper shows them in figures only); the
+  constant rule is pinned by the worked example of Section 2.1.2.
 * a detail is zeroed when ``|c| < thr`` (strict).
 * the bl53 transform keeps L <= J - 1 levels on a 2^J + 1 tile, the largest
   number for which the level update exists and conserves mass.
