@@ -123,3 +123,40 @@ def test_patch_shape_tuner_compares_at_equal_error():
     ok = [r for r in res["shapes"] if r["rel_l2"] <= (1 + res["tolerance"]) * best]
     fastest = max(ok, key=lambda r: r["mlups_events"])
     assert (res["chosen"]["patch"], res["chosen"]["levels"]) == (fastest["patch"], fastest["levels"])
+
+
+@pytest.mark.parametrize("persistent,graph", MODES[1:])
+def test_modes_match_plain_launches_with_per_patch_controls(persistent, graph):
+    """The step-kernel variant with per-patch thresholds, level counts and the
+    network-input export, in every execution mode, against plain launches; the
+    controls are switched off and on again between calls (the graph chunks are
+    rebuilt for the other variant)."""
+    _say("mode with per-patch controls", persistent, graph)
+    rng = np.random.default_rng(31)
+    base = _lbm()
+    other = _lbm()
+    other.set_execution(persistent, graph)
+    npatch = (256 // 64) ** 2
+    eps = 10.0 ** rng.uniform(-5, -3, npatch)
+    lev = rng.integers(2, 6, npatch)
+    for c in (base, other):
+        c.set_patch_eps(eps)
+        c.set_patch_levels(lev)
+        c.enable_features(True)
+    for n in (7, 6):
+        base.step(n)
+        other.step(n)
+        _same(base, other)
+        assert np.array_equal(base.features(), other.features())
+    for c in (base, other):          # back to the uniform variant, then controls again
+        c.set_patch_eps(None)
+        c.set_patch_levels(None)
+        c.enable_features(False)
+    base.step(6)
+    other.step(6)
+    _same(base, other)
+    for c in (base, other):
+        c.set_patch_eps(eps)
+    base.step(7)
+    other.step(7)
+    _same(base, other)
