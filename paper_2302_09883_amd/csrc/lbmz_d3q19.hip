@@ -665,7 +665,7 @@ __device__ __forceinline__ void collide_node(float* fi, float om) {
 // Accesses outside the slice read 0 and write nothing.
 template <class C>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t scratch_rsrc(float* scr) {
-  return __builtin_amdgcn_make_buffer_rsrc(scr, 0, (int)(sizeof(float) * C::M * C::SF), 0x00020000);
+  return __builtin_amdgcn_make_buffer_rsrc(scr, 0, (int)(sizeof(float) * C::M * C::SF), BUF_WORD3);
 }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));

@@ -136,6 +136,13 @@ struct Smem {
 // Small device helpers
 // ---------------------------------------------------------------------------
 
+// Word 3 of the buffer descriptors built here (raw, unswizzled, stride 0):
+// data format 32-bit (bits 15..18 = 4; a zero format makes every access
+// return 0 and write nothing), all other fields 0.  With stride 0 an access
+// is in range when its offset is below the descriptor's byte count; outside
+// it a load returns 0 and a store writes nothing.
+constexpr int BUF_WORD3 = 0x00020000;
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
@@ -1162,7 +1169,7 @@ __device__ __forceinline__ void gather_owned(const uint8_t* rec, uint32_t nnz, u
   constexpr uint32_t B = sizeof(T);
   constexpr uint32_t OUTSIDE = 0x80000000u;   // beyond any record (at most 64 KB)
   const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(rec), 0, (int)(nnz * B), 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(rec), 0, (int)(nnz * B), BUF_WORD3);
   auto word = [&](int k) { return k < 64 ? readlane64(w0, k) : readlane64(w1, k - 64); };
   uint32_t pk = 0u;   // values before the current word
   unsigned long long wk = 0ull;
@@ -1353,9 +1360,9 @@ __device__ __forceinline__ int store_owned_rows(const T* v, unsigned long long a
                                                 uint32_t nnz, uint32_t vb, unsigned long long& myw) {
   constexpr uint32_t B = sizeof(T);
   constexpr uint32_t OUTSIDE = 0x80000000u;   // beyond any record (at most 64 KB)
-  const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(rec, 0, (int)(nnz * B), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(rec, 0, (int)(nnz * B), BUF_WORD3);
   const __amdgpu_buffer_rsrc_t ri =
-      __builtin_amdgcn_make_buffer_rsrc(rec + vb, 0, MASK ? 0 : (int)(2u * nnz), 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc(rec + vb, 0, MASK ? 0 : (int)(2u * nnz), BUF_WORD3);
   const int x = lane_of<C>();
   int run = 0;
   unsigned long long wd = 0ull;
