@@ -128,6 +128,7 @@ struct Smem {
   uint32_t vb[C::M];
   uint32_t rb[C::M];
   uint32_t te[2 * C::M];                 // offset-table entries of the patch being expanded
+  uint32_t samples_only;                 // 1: every record of the patch holds coarse samples only
   unsigned misc[5];                      // pool status, allocation base, stop flag, queue slots
   typename std::conditional<VF == VF_F32, NoLds, NarrowLds<C>>::type nq;
 };
@@ -336,6 +337,18 @@ __device__ __forceinline__ void bl53_inv(T* v) {
     v[(2 * k + 1) * st] = v[(2 * k + 1) * st] + (v[2 * k * st] + v[(2 * k + 2) * st]) * T(0.5);
 }
 
+// The predict half of bl53_inv alone.  When every detail of the line is
+// zero, each update of bl53_inv subtracts exact zeros and returns its sample
+// unchanged, so the predicts alone give the same bits.
+template <class T, int S, int LEV>
+__device__ __forceinline__ void bl53_inv_predict(T* v) {
+  constexpr int st = 1 << (LEV - 1);
+  constexpr int m = (S - 1) / (2 * st);
+#pragma unroll
+  for (int k = 0; k < m; ++k)
+    v[(2 * k + 1) * st] = v[(2 * k + 1) * st] + (v[2 * k * st] + v[(2 * k + 2) * st]) * T(0.5);
+}
+
 // Haar lifting on 2^J nodes: d = b - a, s = a + d / 2 (pairwise mean).
 template <class T, int S, int LEV>
 __device__ __forceinline__ void haar_fwd(T* v) {
@@ -378,6 +391,17 @@ struct Lift {
       if (LEV <= L) {
         Lift<T, S, WAV, LEV + 1, LMAX>::inv(v, L);
         if constexpr (WAV == W_BL53) bl53_inv<T, S, LEV>(v); else haar_inv<T, S, LEV>(v);
+      }
+    }
+  }
+  // BL5/3 inverse of a line whose details are all zero (its only nonzero
+  // entries are coarse samples): the predicts alone, the same bits as inv.
+  static __device__ __forceinline__ void inv_samples(T* v, int L) {
+    static_assert(WAV == W_BL53, "BL5/3 only");
+    if constexpr (LEV <= LMAX) {
+      if (LEV <= L) {
+        Lift<T, S, WAV, LEV + 1, LMAX>::inv_samples(v, L);
+        bl53_inv_predict<T, S, LEV>(v);
       }
     }
   }
@@ -721,15 +745,26 @@ enum RowMode : int {
   ROW_INV_DENSE = 4   // inverse, then owned nodes to the dense output
 };
 
-template <class C, class T, int WAV, int SCH, int MODE>
+// SAMPLES: an inverse pass at the full level count over a tile whose
+// coefficients are coarse samples only (after its column inverse, every row
+// is zero but at the sample columns, and its details are zero): only those
+// entries are read, and the predicts alone invert the row.
+template <class C, class T, int WAV, int SCH, int MODE, bool SAMPLES = false>
 __device__ __forceinline__ void row_pass(const PatchArgs& a, int q, T* tile, const T* ghost) {
   using LF = Lift<T, C::S, WAV, 1, C::LMAX>;
   int f, y;
   if (pass_line<C>(f, y)) {
     const int fb = field_base<C>(f);
     T v[C::S];
-    load_row<C>(v, tile, fb, y);
-    if constexpr (MODE == ROW_FWD) LF::fwd(v, a.levels); else LF::inv(v, a.levels);
+    if constexpr (SAMPLES) {
+      constexpr int SMASK = (1 << C::LMAX) - 1;   // the full level count (checked by the caller)
+#pragma unroll
+      for (int x = 0; x < C::S; ++x) v[x] = ((x & SMASK) == 0) ? tile[fb + y * C::RS + x] : T(0);
+      LF::inv_samples(v, C::LMAX);
+    } else {
+      load_row<C>(v, tile, fb, y);
+      if constexpr (MODE == ROW_FWD) LF::fwd(v, a.levels); else LF::inv(v, a.levels);
+    }
     if constexpr (MODE == ROW_INV_SHIFT) {
       // Streaming in x through the store address: node x of the row goes to
       // x + c_x; the freed end takes the ghost value (c_x = +1: x = 0 from
@@ -1280,11 +1315,15 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
       store_col<C>(v, sm.tile, field_base<C>(f), C::P);
     }
   }
+  // samples_only (set at the start of the patch) is cleared by a bitmask
+  // record here and by a detail in the scatter below
+  if (tid < C::M && (tel(2 * tid + 1) & MASK_BIT)) sm.samples_only = 0u;
   __syncthreads();
   LBMZ_MARK(12);
 
   // Index-list records: scatter, then their columns.
   if (helper) {
+    int nodes = 0;   // OR of the scattered nodes' coordinates
 #pragma unroll
     for (int f = 0; f < C::M; ++f) {
 #pragma unroll
@@ -1294,12 +1333,35 @@ __device__ __forceinline__ void expand_columns(const PatchArgs& a, int q, SM& sm
           int x, y;
           record_node<C>(k, x, y);
           sm.tile[C::Lay::fb(f) + y * C::RS + x] = lr.lv[f][u];
+          nodes |= x | y;
         }
       }
     }
+    // a detail: a node off the lattice of the coarse samples
+    if (__ballot((nodes & ((1 << L) - 1)) != 0) != 0ull && lane == 0) sm.samples_only = 0u;
   }
   __syncthreads();
   LBMZ_MARK(13);
+  if constexpr (!TOT && WAV == W_BL53) {
+    if (L == C::LMAX && __builtin_amdgcn_readfirstlane((int)sm.samples_only) != 0) {
+      // Coarse samples only (at the full level count, so their positions are
+      // known at compile time): the tile is zero but at the samples; only
+      // the sample columns have anything to invert, and their details are zero.
+      constexpr int SMASK = (1 << C::LMAX) - 1;
+      int f, x;
+      const bool line = pass_line<C>(f, x);
+      if (line && (x & SMASK) == 0) {
+        const T* col = sm.tile + field_base<C>(f) + x;
+        T v[C::S];
+#pragma unroll
+        for (int y = 0; y < C::S; ++y) v[y] = ((y & SMASK) == 0) ? col[y * C::RS] : T(0);
+        LF::inv_samples(v, C::LMAX);
+        store_col<C>(v, sm.tile, field_base<C>(f), x);
+      }
+      __syncthreads();
+      return;
+    }
+  }
   bool any_list = false;
 #pragma unroll
   for (int g = 0; g < C::M; ++g) any_list |= !(te(2 * g + 1) & MASK_BIT);
@@ -1627,6 +1689,7 @@ __device__ __forceinline__ bool compact_any(const PatchArgs& a, int q, SM& sm) {
 // zeroing of the fields' owned rows, between the loads and their LDS stores.
 template <class C, class T, int SCH, int VF, class SM>
 __device__ __forceinline__ void begin_patch(const PatchArgs& a, int q, SM& sm, ListRegs<C, T>& lr) {
+  if (tid_of<C>() == 0) sm.samples_only = 1u;   // until the expansion finds a bitmask record or a detail
   if constexpr (VF == VF_F32) prefetch_lists<C, T>(a, q, lr);
   if constexpr (SCH == S_LBM && VF == VF_F32) {
     // The ghost value and the table entry of each thread are loaded into
@@ -1659,7 +1722,15 @@ __device__ __forceinline__ void step_one_patch(const PatchArgs& a, int q, SM& sm
   LBMZ_MARK(14);
   expand_any<C, T, WAV, false, VF, SCH == S_LBM && VF == VF_F32>(a, q, sm, lr);
   LBMZ_MARK(1);
-  row_pass<C, T, WAV, SCH, SCH == S_LBM ? ROW_INV_SHIFT : ROW_INV>(a, q, sm.tile, sm.ghost);
+  constexpr int INV = SCH == S_LBM ? ROW_INV_SHIFT : ROW_INV;
+  if constexpr (VF == VF_F32 && WAV == W_BL53) {
+    if (a.levels == C::LMAX && __builtin_amdgcn_readfirstlane((int)sm.samples_only) != 0)
+      row_pass<C, T, WAV, SCH, INV, true>(a, q, sm.tile, sm.ghost);
+    else
+      row_pass<C, T, WAV, SCH, INV>(a, q, sm.tile, sm.ghost);
+  } else {
+    row_pass<C, T, WAV, SCH, INV>(a, q, sm.tile, sm.ghost);
+  }
   __syncthreads();
   LBMZ_MARK(2);
   if constexpr (SCH == S_LBM) stencil_lbm<C, T>(a, sm.tile);
@@ -1780,6 +1851,7 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
     return;
   }
   ListRegs<C, T> lr;
+  if (threadIdx.x == 0) sm.samples_only = 1u;   // until the expansion finds a bitmask record or a detail
   if constexpr (VF == VF_F32) prefetch_lists<C, T>(a, q, lr);
   prefetch_table<C>(a, q, sm);
   __syncthreads();
