@@ -408,3 +408,41 @@ def test_repeat_runs_are_identical():
     assert np.array_equal(res[0][0], res[1][0])
     assert np.array_equal(res[0][1], res[1][1])
     assert res[0][2] == res[1][2]
+
+
+@pytest.mark.parametrize("levels", [5, 3])
+def test_one_step_with_samples_only_patches(levels):
+    """Every other patch stores its coarse samples alone (no detail in any
+    field): at the full level count the step inverts those patches from the
+    samples with the predict steps only, at fewer levels through the general
+    path.  The decompressed store and one step against the oracle."""
+    n, p = 256, 64
+    eps = 1e-4
+    _say("one-step samples-only patches", levels)
+    ctx = make_ctx(n, "d2q9_bgk", "f32", p, "bl53", levels, eps)
+    twin = oracle_twin(ctx)
+    twin.set_grid(_initial_state(n, "d2q9_bgk", ctx.np_dtype, seed=11))
+    twin.step(1)
+    coef = twin.coef.copy()
+    idx = np.arange(p + 1)
+    lattice = (idx % (1 << levels)) == 0
+    samples = lattice[:, None] & lattice[None, :]
+    coef[::2] = np.where(samples, coef[::2], 0)        # even patches: coarse samples only
+    assert np.count_nonzero(coef[1::2][:, :, ~samples]) > 0
+    twin.set_coefficients(coef, threshold=False)
+    table, pool = O.encode_store(twin.coef)
+    ctx.put_store(table, pool)
+    u = np.finfo(ctx.np_dtype).eps
+    scale = float(np.max(np.abs(twin.grid())))
+    assert np.max(np.abs(ctx.fields() - twin.grid())) <= 16 * u * scale
+    ctx.step(1)
+    twin.step(1)
+    got, _, _ = gpu_coefficients(ctx)
+    want = twin.coef
+    delta = _coef_bound(ctx.np_dtype, scale)
+    thr = np.broadcast_to(twin.thr, want.shape)
+    kg, kw = got != 0, want != 0
+    flip = kg != kw
+    assert np.all(borderline(np.where(kg, got, want), thr, delta)[flip]), int(flip.sum())
+    both = kg & kw
+    assert float(np.max(np.abs(got[both] - want[both]), initial=0.0)) <= delta
