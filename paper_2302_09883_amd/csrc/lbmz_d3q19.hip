@@ -175,6 +175,73 @@ __device__ __forceinline__ void inverse3(float* tile, int L) {
   line_pass<C, 0, false>(tile, L);
 }
 
+// inverse3 of a tile whose coefficients are coarse samples only (nonzero at
+// most on the lattice of nodes whose three indices are multiples of 2^LC).
+// At each pass only the lines through that lattice along the axes already
+// inverted are nonzero, their details are zero, and the predict steps alone
+// invert them: the other lines stay zero and each update would subtract
+// exact zeros, so the bits are those of inverse3.  LC is a compile-time
+// level count, so that the lattice positions are constants.
+template <class C, int LC>
+__device__ void inverse3_samples_l(float* tile) {
+  using LF = Lift<float, C::S, W_BL53, 1, C::LMAX>;
+  constexpr int SMASK = (1 << LC) - 1;
+  // z-lines (x, y) with x and y on the lattice
+  for (int l = threadIdx.x; l < C::S2; l += C::NT) {
+    const int y = l / C::S;
+    const int x = l - y * C::S;
+    if (((x | y) & SMASK) == 0) {
+      float v[C::S];
+#pragma unroll
+      for (int k = 0; k < C::S; ++k) v[k] = (k & SMASK) == 0 ? tile[l + k * C::S2] : 0.f;
+      LF::inv_samples(v, LC);
+#pragma unroll
+      for (int k = 0; k < C::S; ++k) tile[l + k * C::S2] = v[k];
+    }
+  }
+  __syncthreads();
+  // y-lines (x, z) with x on the lattice
+  for (int l = threadIdx.x; l < C::S2; l += C::NT) {
+    const int z = l / C::S;
+    const int x = l - z * C::S;
+    if ((x & SMASK) == 0) {
+      const int base = x + z * C::S2;
+      float v[C::S];
+#pragma unroll
+      for (int k = 0; k < C::S; ++k) v[k] = (k & SMASK) == 0 ? tile[base + k * C::S] : 0.f;
+      LF::inv_samples(v, LC);
+#pragma unroll
+      for (int k = 0; k < C::S; ++k) tile[base + k * C::S] = v[k];
+    }
+  }
+  __syncthreads();
+  // x-lines, every one
+  for (int l = threadIdx.x; l < C::S2; l += C::NT) {
+    const int base = l * C::S;
+    float v[C::S];
+#pragma unroll
+    for (int k = 0; k < C::S; ++k) v[k] = (k & SMASK) == 0 ? tile[base + k] : 0.f;
+    LF::inv_samples(v, LC);
+#pragma unroll
+    for (int k = 0; k < C::S; ++k) tile[base + k] = v[k];
+  }
+  __syncthreads();
+}
+
+// The samples-only inverse for a run-time level count 2 <= L <= LMAX.
+template <class C, int LC = 2>
+__device__ __forceinline__ void inverse3_samples(float* tile, int L) {
+  if constexpr (LC <= C::LMAX) {
+    if (L == LC) inverse3_samples_l<C, LC>(tile);
+    else inverse3_samples<C, LC + 1>(tile, L);
+  }
+}
+
+// Flags of the step in Smem3::misc: the record just expanded holds coarse
+// samples only; the nonzero lattice nodes of the tile being compacted; its
+// record holds coarse samples only.
+constexpr int MISC_SAMPLES_IN = 5, MISC_LATTICE = 6, MISC_SAMPLES_OUT = 7;
+
 // Optional per-phase clocks of the 3-D step (profiling builds compiled with
 // -DLBMZ_PHASE_CLOCK; the product build has none): accumulated wall-clock
 // ticks per workgroup and phase.
@@ -215,6 +282,7 @@ __device__ void expand_field(const PatchArgs& a, int q, int f, SM& sm) {
   const uint32_t vb = (4u * nnz + 7u) & ~7u;
   if (w & MASK_BIT) {
     const unsigned long long* words = reinterpret_cast<const unsigned long long*>(rec + vb);
+    if (tid == 0) sm.misc[MISC_SAMPLES_IN] = 0u;   // a dense record
     if (tid < C::W) sm.pre[tid] = (uint32_t)__popcll(words[tid]);
     __syncthreads();
     scan_counts<C>(sm.pre, C::W, sm);
@@ -249,10 +317,27 @@ __device__ void expand_field(const PatchArgs& a, int q, int f, SM& sm) {
       k0 = idx[tid];
       v0 = vals[tid];
     }
+    if (tid == 0) sm.misc[MISC_SAMPLES_IN] = 1u;   // until a node off the sample lattice is scattered
     zero_span<float>(sm.tile, C::S3, tid, C::NT);
     __syncthreads();
-    if (k0 >= 0) sm.tile[k0] = v0;
-    for (int k = tid + C::NT; k < (int)nnz; k += C::NT) sm.tile[idx[k]] = vals[k];
+    const int lm = (1 << a.levels) - 1;
+    auto off_lattice = [lm](int t) {
+      const int z = t / C::S2;
+      const int r = t - z * C::S2;
+      const int y = r / C::S;
+      return ((r - y * C::S) | y | z) & lm;
+    };
+    int det = 0;
+    if (k0 >= 0) {
+      sm.tile[k0] = v0;
+      det |= off_lattice(k0);
+    }
+    for (int k = tid + C::NT; k < (int)nnz; k += C::NT) {
+      const int t = idx[k];
+      sm.tile[t] = vals[k];
+      det |= off_lattice(t);
+    }
+    if (__ballot(det != 0) != 0ull && lane == 0) sm.misc[MISC_SAMPLES_IN] = 0u;
   }
   __syncthreads();
 }
@@ -322,6 +407,17 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
     const int c = wave + C::NW * lane;
     if (c < C::W) sm.pre[c] = (uint32_t)mycnt;
   }
+  // the nonzero nodes of the sample lattice (L >= 2: at most NT of them),
+  // for the samples-only test of the record below
+  if (L >= 2) {
+    const int nl = ((C::S - 1) >> L) + 1;
+    if (tid < nl * nl * nl) {
+      const int i = tid % nl, j = (tid / nl) % nl, k = tid / (nl * nl);
+      const bool nz = sm.tile[(i << L) + C::S * ((j << L) + C::S * (k << L))] != 0.f;
+      const unsigned long long b = __ballot(nz);
+      if (lane == 0 && b != 0ull) atomicAdd(&sm.misc[MISC_LATTICE], (uint32_t)__popcll(b));
+    }
+  }
   __syncthreads();
   P3_MARK(10);
   const uint32_t nnz = scan_counts<C>(sm.pre, C::W, sm);
@@ -343,6 +439,8 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
     }
     sm.misc[0] = ok ? 1u : 0u;
     sm.misc[1] = (uint32_t)base;
+    // the record holds coarse samples only when every kept node is on the lattice
+    sm.misc[MISC_SAMPLES_OUT] = (L >= 2 && nnz == sm.misc[MISC_LATTICE]) ? 1u : 0u;
   }
   __syncthreads();
   P3_MARK(12);
@@ -736,7 +834,8 @@ __device__ void step_patch(const PatchArgs& a, int q, float* scr, SM& sm) {
   for (int f = 0; f < C::M; ++f) {
     expand_field<C>(a, q, f, sm);
     P3_MARK(0);
-    inverse3<C>(sm.tile, L);
+    if (L >= 2 && __builtin_amdgcn_readfirstlane((int)sm.misc[MISC_SAMPLES_IN]) != 0) inverse3_samples<C>(sm.tile, L);
+    else inverse3<C>(sm.tile, L);
     P3_MARK(1);
     stream_field<C>(a, q, f, scr, sm);
     __syncthreads();
@@ -746,6 +845,7 @@ __device__ void step_patch(const PatchArgs& a, int q, float* scr, SM& sm) {
   __syncthreads();
   P3_MARK(3);
   for (int f = 0; f < C::M; ++f) {
+    if (threadIdx.x == 0) sm.misc[MISC_LATTICE] = 0u;
     load_field<C>(scr + (size_t)f * C::SF, sm);
     P3_MARK(4);
     forward3_threshold<C>(a, sm.tile);
@@ -754,7 +854,8 @@ __device__ void step_patch(const PatchArgs& a, int q, float* scr, SM& sm) {
     P3_MARK(6);
     total_field<C, true>(a, q, f, sm);
     P3_MARK(7);
-    inverse3<C>(sm.tile, a.levels);
+    if (L >= 2 && __builtin_amdgcn_readfirstlane((int)sm.misc[MISC_SAMPLES_OUT]) != 0) inverse3_samples<C>(sm.tile, L);
+    else inverse3<C>(sm.tile, L);
     P3_MARK(8);
     export_field<C>(a, q, f, sm);
     __syncthreads();
