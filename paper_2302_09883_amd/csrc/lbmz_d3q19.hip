@@ -111,24 +111,29 @@ __device__ __forceinline__ uint32_t mbcnt64(unsigned long long m) {
 // the line, the z rank is that of the element (a compile-time index).  A
 // detail (a detail in at least one dimension) with |c| < eps * 2^r is zeroed,
 // r = max (capped), sum (accumulation) or 0 (constant) of the three ranks.
+// Returns true when the line keeps a detail.
 template <class C>
-__device__ __forceinline__ void threshold_zline(float* v, int x, int y, int L, float eps, int rule) {
+__device__ __forceinline__ bool threshold_zline(float* v, int x, int y, int L, float eps, int rule) {
   const int rx = dim_rank(x, L), ry = dim_rank(y, L);
   const bool dxy = rx >= 0 || ry >= 0;
   const int ax = rx < 0 ? 0 : rx, ay = ry < 0 ? 0 : ry;
   const int rmax = ax > ay ? ax : ay, rsum = ax + ay;
   const int lmask = (1 << L) - 1;
+  bool kept = false;
 #pragma unroll
   for (int k = 0; k < C::S; ++k) {
     const bool zs = (k & lmask) == 0;
     const int rz = zs ? 0 : L - 1 - __builtin_ctz((unsigned)(k == 0 ? 1 : k));
     const int r = rule == R_CAPPED ? (rmax > rz ? rmax : rz) : (rule == R_ACCUM ? rsum + rz : 0);
     if ((dxy || !zs) && fabsf(v[k]) < ldexpf(eps, r)) v[k] = 0.f;
+    kept |= (dxy || !zs) && v[k] != 0.f;
   }
+  return kept;
 }
 
 template <class C, int DIR, bool FWD, bool THR = false>
-__device__ __forceinline__ void line_pass(float* tile, int L, float eps = 0.f, int rule = 0) {
+__device__ __forceinline__ void line_pass(float* tile, int L, float eps = 0.f, int rule = 0,
+                                          uint32_t* samples_only = nullptr) {
   using LF = Lift<float, C::S, W_BL53, 1, C::LMAX>;
   for (int l = threadIdx.x; l < C::S2; l += C::NT) {
     int base, stride;
@@ -151,7 +156,7 @@ __device__ __forceinline__ void line_pass(float* tile, int L, float eps = 0.f, i
     if constexpr (THR) {
       static_assert(DIR == 2, "the threshold rides on the last (z) forward pass");
       const int y = l / C::S;
-      threshold_zline<C>(v, l - y * C::S, y, L, eps, rule);
+      if (threshold_zline<C>(v, l - y * C::S, y, L, eps, rule)) *samples_only = 0u;
     }
 #pragma unroll
     for (int k = 0; k < C::S; ++k) tile[base + k * stride] = v[k];
@@ -160,12 +165,14 @@ __device__ __forceinline__ void line_pass(float* tile, int L, float eps = 0.f, i
 }
 
 // Forward transform x, y, z, and the hard threshold of Section 2.2 fused into
-// the z pass.
+// the z pass.  *samples_only ends up 1 when no detail survives the threshold,
+// i.e. when every kept coefficient is a coarse sample.
 template <class C>
-__device__ __forceinline__ void forward3_threshold(const PatchArgs& a, float* tile) {
+__device__ __forceinline__ void forward3_threshold(const PatchArgs& a, float* tile, uint32_t* samples_only) {
+  if (threadIdx.x == 0) *samples_only = 1u;   // until a line keeps a detail (after two barriers)
   line_pass<C, 0, true>(tile, a.levels);
   line_pass<C, 1, true>(tile, a.levels);
-  line_pass<C, 2, true, true>(tile, a.levels, (float)a.eps, a.rule);
+  line_pass<C, 2, true, true>(tile, a.levels, (float)a.eps, a.rule, samples_only);
 }
 
 template <class C>
@@ -238,9 +245,8 @@ __device__ __forceinline__ void inverse3_samples(float* tile, int L) {
 }
 
 // Flags of the step in Smem3::misc: the record just expanded holds coarse
-// samples only; the nonzero lattice nodes of the tile being compacted; its
-// record holds coarse samples only.
-constexpr int MISC_SAMPLES_IN = 5, MISC_LATTICE = 6, MISC_SAMPLES_OUT = 7;
+// samples only; the thresholded tile being compacted keeps coarse samples only.
+constexpr int MISC_SAMPLES_IN = 5, MISC_SAMPLES_OUT = 7;
 
 // Optional per-phase clocks of the 3-D step (profiling builds compiled with
 // -DLBMZ_PHASE_CLOCK; the product build has none): accumulated wall-clock
@@ -347,13 +353,95 @@ __device__ void expand_field(const PatchArgs& a, int q, int f, SM& sm) {
 // appended to the output pool.  Returns false when the pool is full (flag
 // raised).
 // ---------------------------------------------------------------------------
-template <class C, bool THR, class SM>
+// Room for a record of nnz values (bitmask or index list) in the output pool
+// and its table entry; thread 0 reserves, every thread gets the base (16-byte
+// units) in sm.misc[1], or false when the pool is full.
+template <class C, class SM>
+__device__ __forceinline__ bool reserve_record(const PatchArgs& a, int q, int f, uint32_t nnz, bool ismask,
+                                               uint32_t rb16, SM& sm) {
+  if (threadIdx.x == 0) {
+    const unsigned long long base = atomicAdd(&a.ctrl->top16[a.epoch % 3u], (unsigned long long)rb16);
+    const bool ok = base + rb16 <= a.cap16;
+    if (!ok) {
+      atomicOr(&a.ctrl->abort, ABORT_OVERFLOW);
+      atomicMin(&a.ctrl->abort_epoch, a.epoch);
+    } else {
+      const size_t e = 2 * ((size_t)q * C::M + f);
+      a.table_out[e] = (uint32_t)base;
+      a.table_out[e + 1] = nnz | (ismask ? MASK_BIT : 0u);
+    }
+    sm.misc[0] = ok ? 1u : 0u;
+    sm.misc[1] = (uint32_t)base;
+  }
+  __syncthreads();
+  return sm.misc[0] != 0u;
+}
+
+// S7 for a tile that keeps coarse samples only (L >= 2): the kept nodes lie on
+// the lattice of nodes whose three indices are multiples of 2^L, at most NT
+// of them, so one pass over that lattice in ascending flat order gives the
+// index-list record the general compaction below writes, byte for byte.
+template <class C, class SM>
+__device__ bool compact_samples(const PatchArgs& a, int q, int f, SM& sm) {
+  constexpr int NLMAX = (C::S - 1) / 4 + 1;   // lattice nodes per dimension at L = 2
+  static_assert(NLMAX * NLMAX * NLMAX <= C::NT, "one lattice node per thread");
+  static_assert(2 * NLMAX * NLMAX * NLMAX < 8 * C::W, "a samples-only record is an index list");
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const int L = a.levels;
+  const int nl = ((C::S - 1) >> L) + 1;
+  int t = 0;
+  float v = 0.f;
+  if (tid < nl * nl * nl) {
+    const int k = tid / (nl * nl);
+    const int r = tid - k * nl * nl;
+    const int j = r / nl;
+    const int i = r - j * nl;
+    t = (i << L) + C::S * (j << L) + C::S2 * (k << L);
+    v = sm.tile[t];
+  }
+  const unsigned long long bits = __ballot(v != 0.f);
+  if (lane == 0) sm.wsum[wave] = (uint32_t)__popcll(bits);
+  __syncthreads();
+  uint32_t off = 0, nnz = 0;
+  for (int w = 0; w < C::NW; ++w) {
+    const uint32_t c = sm.wsum[w];
+    off += (w < wave) ? c : 0u;
+    nnz += c;
+  }
+  const uint32_t vb = (4u * nnz + 7u) & ~7u;
+  const uint32_t mb = 2u * nnz;
+  const uint32_t rb16 = (vb + mb + 15u) / 16u;
+  if (!reserve_record<C>(a, q, f, nnz, false, rb16, sm)) return false;
+  uint8_t* rec = a.pool_out + 16ull * sm.misc[1];
+  float* vals = reinterpret_cast<float*>(rec);
+  uint16_t* idx = reinterpret_cast<uint16_t*>(rec + vb);
+  if (v != 0.f) {
+    const uint32_t k = off + mbcnt64(bits);
+    vals[k] = v;
+    idx[k] = (uint16_t)t;
+  }
+  if (tid == 0 && (nnz & 1u)) vals[nnz] = 0.f;
+  const uint32_t tail0 = (vb + mb) / 2u, tail1 = rb16 * 8u;
+  uint16_t* h = reinterpret_cast<uint16_t*>(rec);
+  if (tid < (int)(tail1 - tail0)) h[tail0 + tid] = 0;
+  return true;
+}
+
+// SAMPLES: the step path, where forward3_threshold has left the samples-only
+// flag in sm.misc[MISC_SAMPLES_OUT].
+template <class C, bool THR, bool SAMPLES = false, class SM>
 __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = wave_id();
   const int L = a.levels;
   const float eps = (float)a.eps;
+  if constexpr (SAMPLES) {
+    if (L >= 2 && __builtin_amdgcn_readfirstlane((int)sm.misc[MISC_SAMPLES_OUT]) != 0)
+      return compact_samples<C>(a, q, f, sm);
+  }
   P3_START();
   // counts: one ballot per 64-node chunk; wave w owns the chunks
   // c = w + NW k, keeps bit k of `nonempty` for those with a kept
@@ -407,17 +495,6 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
     const int c = wave + C::NW * lane;
     if (c < C::W) sm.pre[c] = (uint32_t)mycnt;
   }
-  // the nonzero nodes of the sample lattice (L >= 2: at most NT of them),
-  // for the samples-only test of the record below
-  if (L >= 2) {
-    const int nl = ((C::S - 1) >> L) + 1;
-    if (tid < nl * nl * nl) {
-      const int i = tid % nl, j = (tid / nl) % nl, k = tid / (nl * nl);
-      const bool nz = sm.tile[(i << L) + C::S * ((j << L) + C::S * (k << L))] != 0.f;
-      const unsigned long long b = __ballot(nz);
-      if (lane == 0 && b != 0ull) atomicAdd(&sm.misc[MISC_LATTICE], (uint32_t)__popcll(b));
-    }
-  }
   __syncthreads();
   P3_MARK(10);
   const uint32_t nnz = scan_counts<C>(sm.pre, C::W, sm);
@@ -426,25 +503,9 @@ __device__ bool compact_field(const PatchArgs& a, int q, int f, SM& sm) {
   const uint32_t vb = (4u * nnz + 7u) & ~7u;
   const uint32_t mb = ismask ? 8u * (uint32_t)C::W : 2u * nnz;
   const uint32_t rb16 = (vb + mb + 15u) / 16u;
-  if (tid == 0) {
-    const unsigned long long base = atomicAdd(&a.ctrl->top16[a.epoch % 3u], (unsigned long long)rb16);
-    const bool ok = base + rb16 <= a.cap16;
-    if (!ok) {
-      atomicOr(&a.ctrl->abort, ABORT_OVERFLOW);
-      atomicMin(&a.ctrl->abort_epoch, a.epoch);
-    } else {
-      const size_t e = 2 * ((size_t)q * C::M + f);
-      a.table_out[e] = (uint32_t)base;
-      a.table_out[e + 1] = nnz | (ismask ? MASK_BIT : 0u);
-    }
-    sm.misc[0] = ok ? 1u : 0u;
-    sm.misc[1] = (uint32_t)base;
-    // the record holds coarse samples only when every kept node is on the lattice
-    sm.misc[MISC_SAMPLES_OUT] = (L >= 2 && nnz == sm.misc[MISC_LATTICE]) ? 1u : 0u;
-  }
-  __syncthreads();
+  const bool ok = reserve_record<C>(a, q, f, nnz, ismask, rb16, sm);
   P3_MARK(12);
-  if (!sm.misc[0]) return false;
+  if (!ok) return false;
   uint8_t* rec = a.pool_out + 16ull * sm.misc[1];
   float* vals = reinterpret_cast<float*>(rec);
   uint16_t* idx = reinterpret_cast<uint16_t*>(rec + vb);
@@ -845,12 +906,11 @@ __device__ void step_patch(const PatchArgs& a, int q, float* scr, SM& sm) {
   __syncthreads();
   P3_MARK(3);
   for (int f = 0; f < C::M; ++f) {
-    if (threadIdx.x == 0) sm.misc[MISC_LATTICE] = 0u;
     load_field<C>(scr + (size_t)f * C::SF, sm);
     P3_MARK(4);
-    forward3_threshold<C>(a, sm.tile);
+    forward3_threshold<C>(a, sm.tile, &sm.misc[MISC_SAMPLES_OUT]);
     P3_MARK(5);
-    compact_field<C, false>(a, q, f, sm);
+    compact_field<C, false, true>(a, q, f, sm);
     P3_MARK(6);
     total_field<C, true>(a, q, f, sm);
     P3_MARK(7);
@@ -903,7 +963,7 @@ __global__ __launch_bounds__(1024) void d3q19_aux_kernel(PatchArgs a) {
         sm.tile[t] = src[((size_t)gz * n + gy) * n + gx];
       }
       __syncthreads();
-      forward3_threshold<C>(a, sm.tile);
+      forward3_threshold<C>(a, sm.tile, &sm.misc[MISC_SAMPLES_OUT]);
       finish_field<C, false>(a, q, f, sm);
     } else if (a.mode == AUX_COEF) {
       const float* src = static_cast<const float*>(a.coef_in) + ((size_t)q * C::M + f) * C::S3;
