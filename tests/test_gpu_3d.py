@@ -157,6 +157,61 @@ def test_one_step_from_common_state(n, p, levels, eps):
     assert 0 < np.count_nonzero(got) < got.size
 
 
+def _rest_with_bump(n, amp, width):
+    """Fluid at rest (rho = 1, u = 0) but for a density bump of the given width
+    around one point, cut off at three widths: tiles beyond are constant, so
+    their records keep coarse samples only."""
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64),) * 3, indexing="ij")
+    c = n / 4 + 0.5
+    r2 = ((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2) / width ** 2
+    rho = 1.0 + amp * np.exp(-r2) * (r2 < 9.0)
+    zero = np.zeros_like(rho)
+    return O3.d3q19_equilibrium(rho, zero, zero, zero).astype(np.float32)
+
+
+def _samples_only(tile, levels):
+    m = (1 << levels) - 1
+    z, y, x = np.nonzero(tile)
+    return bool(np.all(((x | y | z) & m) == 0))
+
+
+@pytest.mark.parametrize("n,p,levels,eps", [(64, 16, 3, 1e-4), (64, 16, 2, 1e-4), (32, 16, 3, 0.5)])
+def test_step_records_of_samples_only_tiles(n, p, levels, eps):
+    """One step from a state whose records hold coarse samples only in most
+    tiles (constant fluid at rest; at eps = 0.5 every detail of every tile is
+    dropped and the samples differ from node to node), beside tiles with
+    details: every record the step writes is byte for byte the encoding of its
+    own tile, and the tiles match the oracle's step."""
+    _say("3d samples-only step", n, p, levels, eps)
+    g = O3.Geometry3(n, p, levels)
+    twin = O3.CompressedRun3(g, TAU, eps, dtype=np.float32)
+    twin.set_grid(_rest_with_bump(n, 0.02, n / 12 if eps < 0.1 else n / 3))
+    table0, pool0 = twin.store()
+    ctx = _ctx(n, p, levels, eps)
+    ctx.put_store(table0, pool0)
+    ctx.step(1)
+    twin.step(1)
+    got, table, pool = _tiles(ctx)
+    for q in range(g.npatch):
+        for f in range(19):
+            rec = O3.encode_record3(got[q, f])
+            off = int(table[q, f, 0]) * 16
+            assert pool[off:off + len(rec)] == rec, (q, f)
+            assert int(table[q, f, 1]) & (O3.MASK_BIT - 1) == np.count_nonzero(got[q, f])
+    only = np.array([[_samples_only(got[q, f], levels) for f in range(19)] for q in range(g.npatch)])
+    if eps < 0.1:
+        assert 0 < only.sum() < only.size, int(only.sum())
+    else:
+        assert only.all()
+        assert all(len(np.unique(got[q, f][got[q, f] != 0])) > 1 for q in range(g.npatch) for f in range(19))
+    want = twin.coef
+    delta = 1e-5 * float(np.max(np.abs(want)))
+    flip = (got != 0) != (want != 0)
+    near = np.abs(np.abs(np.where(got != 0, got, want)) - twin.thr) <= delta
+    assert np.all(near[flip]), int(flip.sum())
+    assert np.max(np.abs(np.where(flip, 0.0, got - want))) <= delta
+
+
 def test_multi_step_close_to_oracle_and_conserving():
     _say("3d multi step")
     n, p, levels, eps, steps = 48, 16, 3, 1e-4, 8
