@@ -175,7 +175,8 @@ def _samples_only(tile, levels):
     return bool(np.all(((x | y | z) & m) == 0))
 
 
-@pytest.mark.parametrize("n,p,levels,eps", [(64, 16, 3, 1e-4), (64, 16, 2, 1e-4), (32, 16, 3, 0.5)])
+@pytest.mark.parametrize("n,p,levels,eps", [(64, 16, 3, 1e-4), (64, 16, 2, 1e-4), (32, 16, 3, 0.5), (64, 32, 3, 1e-4),
+                                             (64, 32, 2, 1e-4)])
 def test_step_records_of_samples_only_tiles(n, p, levels, eps):
     """One step from a state whose records hold coarse samples only in most
     tiles (constant fluid at rest; at eps = 0.5 every detail of every tile is
