@@ -41,6 +41,7 @@ struct PatchArgs {
   int n;             // grid cells per side
   int npx;           // patches per side
   int npatch;        // patches in the grid
+  int npx_shift;     // log2(npx) when npx is a power of two, else -1
   int levels;        // wavelet levels per dimension
   int rule;          // Rule
   double eps;        // threshold constant

@@ -468,6 +468,19 @@ __device__ __forceinline__ void threshold_column(T* v, int x, int L, T eps, int 
 // Periodic index of a patch coordinate (v within one period of [0, n)).
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Patch coordinates of patch q (row-major): a mask and a shift when the number
+// of patches per side is a power of two, so that the start of a patch does not
+// wait on an integer division.
+__device__ __forceinline__ void patch_xy(const PatchArgs& a, int q, int& px, int& py) {
+  if (a.npx_shift >= 0) {
+    px = q & (a.npx - 1);
+    py = q >> a.npx_shift;
+  } else {
+    px = q % a.npx;
+    py = q / a.npx;
+  }
+}
+
 // Threshold constant of patch q: the per-patch value when one is set.
 __device__ __forceinline__ double patch_eps(const PatchArgs& a, int q) {
   return a.eps_patch ? a.eps_patch[q] : a.eps;
@@ -508,7 +521,8 @@ __device__ __forceinline__ void threshold_patch_column(const PatchArgs& a, int q
   for (int k = 1; k <= C::LMAX + 1; ++k) tl[k] = class_threshold<C, T>(x, k, e0, l0, rule);
   T row0 = tl[C::LMAX + 1], rowp = tl[C::LMAX + 1];   // y = 0 and y = P: sample rows
   if constexpr (C::RIM) {
-    const int px = q % a.npx, py = q / a.npx;
+    int px, py;
+    patch_xy(a, q, px, py);
     if (x == 0 || x == C::P) {
       const int nb = wrap(px + (x == 0 ? -1 : 1), a.npx) + a.npx * py;
       const T e1 = T(patch_eps(a, nb));
@@ -675,8 +689,8 @@ __device__ __forceinline__ void totals_finish(const PatchArgs& a, double* out, i
 template <class C, class T>
 __device__ __forceinline__ T* gather_lbm_at(const PatchArgs& a, int q, int k, T* tile, T* ghost, T& v) {
   const T* h = static_cast<const T*>(a.halo_in);
-  const int px = q % a.npx;
-  const int py = q / a.npx;
+  int px, py;
+  patch_xy(a, q, px, py);
   const int side = k / (3 * C::S);
   const int rem = k - side * (3 * C::S);
   const int slot = rem / C::S;
@@ -709,8 +723,8 @@ __device__ __forceinline__ void gather_lbm(const PatchArgs& a, int q, T* tile, T
 template <class C, class T>
 __device__ __forceinline__ void gather_fv(const PatchArgs& a, int q, T* ghost) {
   const T* h = static_cast<const T*>(a.halo_in);
-  const int px = q % a.npx;
-  const int py = q / a.npx;
+  int px, py;
+  patch_xy(a, q, px, py);
   for (int k = tid_of<C>(); k < 4 * C::NSLOT * C::S; k += C::NT) {
     const int side = k / (C::NSLOT * C::S);
     const int rem = k - side * (C::NSLOT * C::S);
@@ -1818,8 +1832,8 @@ __global__ __launch_bounds__((Cfg<T, P, WAV, SCH>::NT)) void patch_aux_kernel(Pa
   using C = Cfg<T, P, WAV, SCH>;
   __shared__ Smem<C, T, VF> sm;
   const int q = blockIdx.x;
-  const int px = q % a.npx;
-  const int py = q / a.npx;
+  int px, py;
+  patch_xy(a, q, px, py);
   if (a.mode == AUX_INIT || a.mode == AUX_COEF) {
     if (q == 0 && threadIdx.x == 0) a.ctrl->top16[(a.epoch + 1u) % 3u] = 0ull;
     for (int f = 0; f < C::M; ++f) {

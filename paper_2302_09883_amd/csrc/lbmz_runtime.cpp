@@ -635,6 +635,9 @@ int lbmz_create(const lbmz_grid* grid, const lbmz_scheme* scheme, const lbmz_pat
     PatchArgs& a = c->base;
     a.npx = c->npx;
     a.npatch = c->npatch;
+    a.npx_shift = -1;
+    for (int k = 0; (1 << k) <= c->npx; ++k)
+      if ((1 << k) == c->npx) a.npx_shift = k;
     a.levels = c->levels;
     a.rule = c->rule;
     a.eps = c->eps;
