@@ -686,6 +686,25 @@ __device__ __forceinline__ void totals_finish(const PatchArgs& a, double* out, i
 // S/N ghost rows of the tile, already shifted in x: row -1 of population i
 // holds f_i(x - c_ix, -1), row S holds f_i(x - c_ix, S).
 // Ghost value k (0 <= k < 4 * 3 * S): loaded into v; returns its LDS slot.
+// D2Q9::SIDE_POP[side][slot] and D2Q9::CX[pop] for per-lane indices, as shifts
+// of packed constants: an indexed constant array is read from memory, and the
+// two lookups would delay the ghost load of every patch by two dependent loads.
+constexpr unsigned long long side_pop_packed() {
+  unsigned long long v = 0ull;
+  for (int s = 0; s < 4; ++s)
+    for (int k = 0; k < 3; ++k) v |= (unsigned long long)D2Q9::SIDE_POP[s][k] << (4 * (3 * s + k));
+  return v;
+}
+constexpr unsigned int cx_packed() {
+  unsigned int v = 0u;
+  for (int i = 0; i < 9; ++i) v |= (unsigned int)(D2Q9::CX[i] + 1) << (2 * i);
+  return v;
+}
+__device__ __forceinline__ int side_pop(int side, int slot) {
+  return (int)((side_pop_packed() >> (4 * (3 * side + slot))) & 15ull);
+}
+__device__ __forceinline__ int d2q9_cx(int pop) { return (int)((cx_packed() >> (2 * pop)) & 3u) - 1; }
+
 template <class C, class T>
 __device__ __forceinline__ T* gather_lbm_at(const PatchArgs& a, int q, int k, T* tile, T* ghost, T& v) {
   const T* h = static_cast<const T*>(a.halo_in);
@@ -700,8 +719,8 @@ __device__ __forceinline__ T* gather_lbm_at(const PatchArgs& a, int q, int k, T*
     v = h[((size_t)(nb * 4 + side) * 3 + slot) * C::S + j];
     return ghost + k;
   }
-  const int pop = D2Q9::SIDE_POP[side][slot];
-  const int xs = j - D2Q9::CX[pop];
+  const int pop = side_pop(side, slot);
+  const int xs = j - d2q9_cx(pop);
   const int ox = xs < 0 ? -1 : (xs >= C::S ? 1 : 0);
   const int xl = xs - C::P * ox;
   const int nb = wrap(px + ox, a.npx) + a.npx * wrap(py + (side == 2 ? -1 : 1), a.npx);
