@@ -759,11 +759,11 @@ __device__ __forceinline__ void gather_fv(const PatchArgs& a, int q, T* ghost) {
 
 // Slot of D2Q9 population f among those entering through side `side`.
 __device__ __forceinline__ int pop_slot(int side, int f) {
-  return D2Q9::SIDE_POP[side][0] == f ? 0 : (D2Q9::SIDE_POP[side][1] == f ? 1 : 2);
+  return side_pop(side, 0) == f ? 0 : (side_pop(side, 1) == f ? 1 : 2);
 }
 
 __device__ __forceinline__ bool pop_enters(int side, int f) {
-  return D2Q9::SIDE_POP[side][0] == f || D2Q9::SIDE_POP[side][1] == f || D2Q9::SIDE_POP[side][2] == f;
+  return side_pop(side, 0) == f || side_pop(side, 1) == f || side_pop(side, 2) == f;
 }
 
 // ---------------------------------------------------------------------------
